@@ -1,0 +1,157 @@
+"""Pins of the STN oracle against physics that does not depend on it (no GPU).
+
+  * brute-force statevector on memory circuits and random small circuits
+    (no truncation fires): records, p(0) of every measurement, log P;
+  * closed form of Eq. (6) from tests/golden/eq6_single_rotation.json;
+  * theta = 0: records equal the Aaronson-Gottesman simulation, the MPS stays
+    |0...0> with bond 1 and every p(0) is 0, 1/2 or 1;
+  * theta -> -theta leaves every record probability unchanged (all gates but
+    the rotations are real);
+  * the x/z bits of the tableau do not depend on the shot;
+  * a planted sign error in the oracle's rotation is caught.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import chp, statevector, stn
+from paper_2605_29514_amd import workload as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def random_circuit(n, n_layers, n_shots, seed):
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(n_layers):
+        gates = []
+        for _ in range(3):
+            g = ["H", "S", "CX", "CZ"][rng.integers(4)]
+            if g in ("H", "S"):
+                gates.append((g, int(rng.integers(n)), -1))
+            else:
+                a, b = rng.choice(n, 2, replace=False)
+                gates.append((g, int(a), int(b)))
+        ops.append({"op": "gates", "gates": gates})
+        x = rng.random((n_shots, n)) < 0.1
+        z = rng.random((n_shots, n)) < 0.1
+        ops.append({"op": "noise", "x": x, "z": z})
+        R = 3
+        paulis = np.full((R, 3), -1, np.int32)
+        for r in range(R):
+            k = int(rng.integers(2, 4))
+            paulis[r, :k] = rng.choice(n, k, replace=False)
+        ops.append({"op": "rotate", "paulis": paulis,
+                    "theta": rng.uniform(-0.6, 0.6, (n_shots, R)), "param": np.arange(R)})
+        qs = rng.choice(n, 2, replace=False).astype(np.int32)
+        ops.append({"op": "measure", "qubits": qs, "reset": bool(rng.random() < 0.5),
+                    "u": rng.random((n_shots, 2))})
+    return W.Circuit(n, n_shots, ops)
+
+
+def _compare_sv(circ, shots, chi_max=1 << 20, eps=1e-22, tol=1e-11):
+    for s in shots:
+        r = stn.run_shot(circ, s, chi_max=chi_max, eps_cut=eps)
+        rec, probs, p0s, lp, _ = statevector.run_shot(circ, s)
+        assert r.record == rec, s
+        assert np.max(np.abs(np.array(r.p0) - np.array(p0s))) < tol
+        assert abs(r.logp - lp) < 1e-9
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_circuits_match_statevector(seed):
+    _compare_sv(random_circuit(5, 6, 3, seed), range(3))
+
+
+def test_memory_d3_matches_statevector():
+    circ = W.memory_circuit(3, 2, 3, seed=7, theta_nn=0.05, p=0.01)
+    _compare_sv(circ, range(3))
+
+
+def test_memory_d3_per_coupling_nnn_matches_statevector():
+    circ = W.memory_circuit(3, 2, 2, seed=9, theta_law="per_coupling", nnn=True,
+                            theta_range=(0.02, 0.1), p=0.01)
+    _compare_sv(circ, range(2))
+
+
+def test_memory_d3_triples_match_statevector():
+    circ = W.memory_circuit(3, 1, 2, seed=13, theta_nn=0.04, theta_triple=0.01)
+    _compare_sv(circ, range(2))
+
+
+def test_eq6_closed_form():
+    """exp(-i theta ZZ) on |++>, then H and Z-measure qubit 0: p(1) = sin^2 theta."""
+    with open(os.path.join(HERE, "golden", "eq6_single_rotation.json")) as f:
+        fx = json.load(f)
+    for case in fx["cases"]:
+        th = case["theta"]
+        ops = [{"op": "gates", "gates": [("H", 0, -1), ("H", 1, -1)]},
+               {"op": "rotate", "paulis": np.array([[0, 1, -1]], np.int32),
+                "theta": np.array([[th]]), "param": np.array([0])},
+               {"op": "gates", "gates": [("H", 0, -1)]},
+               {"op": "measure", "qubits": np.array([0], np.int32), "reset": False,
+                "u": np.array([[0.999999]])}]
+        r = stn.run_shot(W.Circuit(2, 1, ops), 0)
+        assert abs((1 - r.p0[0]) - case["p_flip"]) < 1e-14
+
+
+@pytest.mark.parametrize("d", [3, 5])
+def test_theta_zero_equals_stabilizer_simulation(d):
+    circ = W.memory_circuit(d, 2, 3, seed=17, theta_nn=0.0, p=0.01)
+    for s in range(3):
+        r = stn.run_shot(circ, s, chi_max=8, eps_cut=1e-16)
+        rec, _ = chp.run_shot(circ, s)
+        assert r.record == rec
+        assert r.max_bond == 1 and max(r.bond_trace) == 1
+        assert set(np.round(r.p0, 15)) <= {0.0, 0.5, 1.0}
+        amp = r.mps.dense() if circ.n <= 20 else None
+        if amp is not None:
+            assert abs(abs(amp[0]) - 1) < 1e-15
+
+
+def test_theta_sign_symmetry():
+    circ = W.memory_circuit(3, 2, 2, seed=19, theta_nn=0.07, p=0.01)
+    neg = W.memory_circuit(3, 2, 2, seed=19, theta_nn=-0.07, p=0.01)
+    for s in range(2):
+        a = stn.run_shot(circ, s, eps_cut=1e-22)
+        b = stn.run_shot(neg, s, forced=a.record, eps_cut=1e-22)
+        assert np.max(np.abs(np.array(a.prob) - np.array(b.prob))) < 1e-12
+
+
+def test_probabilities_and_norm():
+    circ = W.memory_circuit(3, 2, 1, seed=23, theta_nn=0.08, p=0.01)
+    r = stn.run_shot(circ, 0, chi_max=4, eps_cut=1e-14)
+    assert r.trunc_err > 0                       # chi_max=4 binds
+    assert abs(r.mps.norm2() - 1) < 1e-12
+    p0 = np.array(r.p0)
+    assert np.all((p0 >= 0) & (p0 <= 1))
+
+
+def test_tableau_bits_shared_across_shots():
+    circ = W.memory_circuit(3, 2, 4, seed=29, theta_nn=0.05, p=0.02)
+    runs = [stn.run_shot(circ, s, chi_max=16, eps_cut=1e-14) for s in range(4)]
+    for r in runs[1:]:
+        assert np.array_equal(r.tableau.x, runs[0].tableau.x)
+        assert np.array_equal(r.tableau.z, runs[0].tableau.z)
+    assert any(not np.array_equal(r.tableau.e, runs[0].tableau.e) for r in runs[1:])
+
+
+def test_planted_rotation_sign_error_is_caught(monkeypatch):
+    """A dropped factor sigma in the rotation must break statevector parity."""
+    orig = stn.Shot.rotate
+
+    def bad_rotate(self, qubits, theta):
+        p = self.tab.image(stn.z_string(self.n, qubits))
+        sup = p.support()
+        self.mps.apply_two_term(int(sup[0]), int(sup[-1]), np.cos(theta), {},
+                                -1j * np.sin(theta), stn.site_ops(p))
+        self.res.bond_trace.append(1)
+
+    circ = W.memory_circuit(3, 2, 2, seed=7, theta_nn=0.05, p=0.05)
+    monkeypatch.setattr(stn.Shot, "rotate", bad_rotate)
+    with pytest.raises(AssertionError):
+        _compare_sv(circ, range(2))
+    monkeypatch.setattr(stn.Shot, "rotate", orig)
+    _compare_sv(circ, range(2))
