@@ -1,0 +1,194 @@
+/*
+ * stn.h - C ABI of libstn, the MI355X (gfx950) hot path of the hybrid
+ * stabilizer-tensor-network (STN) simulation of surface-code syndrome
+ * extraction under coherent crosstalk (Harper, Nakhl, Sevior, Usman).
+ *
+ * The simulated state is psi = C |MPS> (Sec. IV.A, Eq. 7): a Clifford C held
+ * as a bit-packed inverse tableau and a matrix-product state, for a batch of
+ * independent shots that share one circuit.  Clifford gates only update the
+ * tableau (Sec. IV.A); a crosstalk rotation exp(-i theta P) is rewritten
+ * through the tableau into a Pauli string P' on the MPS, the MPS becomes
+ * cos(theta) phi - i sin(theta) P' phi, and its bonds are cut back to chi_max
+ * by keeping the largest Schmidt values (Sec. IV.A-B, Eqs. 4 and 8); a Z
+ * measurement is commuted through the tableau and projected on the MPS
+ * (Sec. IV.A, last paragraph).
+ *
+ * Conventions shared by every call:
+ *  - Memory: every device buffer is owned by the caller.  The library keeps
+ *    pointers into the workspace given to stn_init and never allocates device
+ *    memory itself.  Pointers named dev_* are device pointers, host_* are
+ *    host pointers.  All work is enqueued on the stream given in stn_config
+ *    (NULL = the default stream); calls return before the work completes
+ *    unless stated otherwise.
+ *  - Threads: a context is used by one host thread at a time.
+ *  - Errors: argument errors are detected on the host and returned at once
+ *    (STN_EINVAL), leaving the context unchanged.  Errors found by kernels
+ *    (an impossible forced outcome, a non-finite number, a non-converged
+ *    eigen-solve) set a device error word; stn_sync, stn_logprob and the
+ *    stn_get_* calls synchronise and report it.  After a device error the
+ *    context state is undefined: free it.  stn_last_error gives a message.
+ *  - Qubits are numbered 0..n_qubits-1 and qubit q is MPS site q.
+ *  - Shot bit-masks are "sign words": uint64 words with bit (s % 64) of word
+ *    (s / 64) belonging to shot s; n_sign_words = ceil(n_shots / 64).
+ */
+#ifndef STN_H
+#define STN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stn_ctx stn_ctx;
+
+typedef enum {
+    STN_OK = 0,
+    STN_EINVAL = -1,     /* bad argument (index out of range, size mismatch, ...) */
+    STN_ENOMEM = -2,     /* workspace too small */
+    STN_EDEVICE = -3,    /* HIP runtime error */
+    STN_EZEROPROB = -4,  /* a forced measurement outcome has probability 0 */
+    STN_ENUMERIC = -5,   /* NaN/Inf, odd tableau phase or eigen-solve failure */
+    STN_ESTATE = -6      /* call not valid in the current state */
+} stn_status;
+
+enum { STN_FP64 = 0,   /* complex128 everywhere */
+       STN_FP32 = 1 }; /* complex64 tensors and contractions; FP64 Gram,
+                          eigen-solve, norms and probabilities */
+
+typedef struct {
+    int n_qubits;        /* chain length n, 1..1024 */
+    int n_shots;         /* independent shots simulated together, >= 1 */
+    int chi_max;         /* bond-dimension cap (Sec. IV.B), 1..512 */
+    int precision;       /* STN_FP64 or STN_FP32 */
+    double eps_cut;      /* drop Schmidt values with lambda^2 <= eps_cut * sum lambda^2 */
+    void *stream;        /* hipStream_t, or NULL for the default stream */
+} stn_config;
+
+/* Gate kinds for stn_clifford.  Two-qubit kinds take (q0 = control, q1 = target). */
+enum { STN_GATE_H = 0, STN_GATE_S = 1, STN_GATE_SDG = 2, STN_GATE_X = 3,
+       STN_GATE_Y = 4, STN_GATE_Z = 5, STN_GATE_CX = 6, STN_GATE_CY = 7,
+       STN_GATE_CZ = 8 };
+
+typedef struct {
+    int32_t kind;        /* STN_GATE_* */
+    int32_t q0, q1;      /* q1 ignored (set -1) for one-qubit gates */
+} stn_gate;
+
+/* Bytes of device workspace stn_init needs for this configuration (0 on a
+ * bad configuration).  The bytes cover the tableau, the MPS of every shot
+ * at its largest possible bonds, the doubled-bond compression workspace and
+ * per-shot scratch. */
+size_t stn_workspace_bytes(const stn_config *cfg);
+
+/* Create a context.  dev_workspace: caller-owned device memory of at least
+ * stn_workspace_bytes(cfg) bytes, 256-byte aligned, kept alive until
+ * stn_free.  Initial state: C = I and MPS = |0...0> for every shot
+ * (Sec. IV.A).  Returns STN_EINVAL / STN_ENOMEM on bad arguments. */
+stn_status stn_init(stn_ctx **out, const stn_config *cfg, void *dev_workspace,
+                    size_t bytes);
+
+/* Release the host-side context (the workspace stays the caller's). */
+void stn_free(stn_ctx *ctx);
+
+/* Message of the last error on this context ("" if none). */
+const char *stn_last_error(const stn_ctx *ctx);
+
+/* Clifford gates: C <- G C for each gate in order; the MPS is untouched
+ * (Sec. IV.A).  host_gates[n_gates] is read before the call returns.  Then,
+ * if dev_noise is not NULL, per-shot Pauli noise (Eqs. 2-3 sampled as
+ * Paulis): dev_noise is uint64 [2][n_qubits][n_sign_words]; plane 0 holds
+ * the shots whose Pauli on that qubit has an X component (X or Y), plane 1
+ * those with a Z component (Z or Y). */
+stn_status stn_clifford(stn_ctx *ctx, const stn_gate *host_gates, int n_gates,
+                        const uint64_t *dev_noise);
+
+/* Crosstalk rotations exp(-i theta_r Z_a Z_b [Z_c]) applied in order (Eq. 4
+ * with the sign read as exp(-i theta P); Sec. IV.A for the rewrite), each
+ * followed by compression to chi_max (Sec. IV.B, Eq. 8).
+ * host_qubits: int32 [n_rot][3], unused entries -1, at least two qubits per
+ * rotation, all distinct.  dev_theta: double angles, theta of rotation r for
+ * shot s at dev_theta[s * theta_shot_stride + r] (stride 0: one angle per
+ * rotation shared by all shots). */
+stn_status stn_rotate(stn_ctx *ctx, const int32_t *host_qubits, int n_rot,
+                      const double *dev_theta, int64_t theta_shot_stride);
+
+/* Z measurements of host_qubits[n_meas] in order (Sec. IV.A).  For each:
+ * p(m) = <phi|(I + (-1)^m P')/2|phi> / <phi|phi> with P' = C^dag Z_q C,
+ * outcome m = 0 iff u < p(0) with u = dev_u[s * n_meas + i] (double in
+ * [0,1)), or m = dev_forced[s * n_meas + i] (uint8) when dev_forced is not
+ * NULL (dev_u is then ignored and may be NULL); the MPS is projected and,
+ * when P' has an X/Y site, the frame absorbs the random part so that a
+ * Clifford-only run keeps bond dimension 1.  reset != 0 applies X_q after
+ * outcome 1.  Outputs (caller-owned device arrays, may be NULL):
+ * dev_outcomes uint8 [n_shots][n_meas], dev_prob double [n_shots][n_meas]
+ * = p(recorded outcome).  A forced outcome of probability 0 sets
+ * STN_EZEROPROB on the device error word. */
+stn_status stn_measure(stn_ctx *ctx, const int32_t *host_qubits, int n_meas,
+                       int reset, const double *dev_u, const uint8_t *dev_forced,
+                       uint8_t *dev_outcomes, double *dev_prob);
+
+/* Per-shot log P(record so far) = sum of log p(recorded outcome), and the
+ * accumulated truncation error 1 - prod(1 - w) over every cut (w = discarded
+ * squared-Schmidt weight, Eq. 8).  dev_logp, dev_trunc_err: double
+ * [n_shots] device arrays (either may be NULL).  Synchronises the stream and
+ * reports the device error word. */
+stn_status stn_logprob(stn_ctx *ctx, double *dev_logp, double *dev_trunc_err);
+
+/* Wait for all enqueued work and report the device error word. */
+stn_status stn_sync(stn_ctx *ctx);
+
+/* Copy the tableau to the host (synchronises): host_x, host_z uint64
+ * [2 n_qubits][ceil(n_qubits/64)] (row q = C^dag X_q C, row n+q = C^dag Z_q C,
+ * bit j%64 of word j/64 = site j), host_sign uint64 [2 n_qubits][n_sign_words]
+ * (bit set = row carries sign -1 for that shot).  Any pointer may be NULL. */
+stn_status stn_get_tableau(stn_ctx *ctx, uint64_t *host_x, uint64_t *host_z,
+                           uint64_t *host_sign);
+
+/* Copy the bond dimensions to the host (synchronises): host_bonds int32
+ * [n_shots][n_qubits + 1], entry b = bond between sites b-1 and b (1 at both
+ * ends). */
+stn_status stn_get_bonds(stn_ctx *ctx, int32_t *host_bonds);
+
+/* Copy one MPS site tensor of one shot to the host (synchronises).  The
+ * tensor (dl, 2, dr) is written row-major as interleaved (re, im) pairs of
+ * double (STN_FP64) or float (STN_FP32); host_buf must hold bytes >= dl*2*dr
+ * complex elements.  *dl, *dr receive the shape. */
+stn_status stn_get_site(stn_ctx *ctx, int shot, int site, void *host_buf,
+                        size_t bytes, int *dl, int *dr);
+
+/* Kernel classes for stn_profile / stn_profile_read. */
+enum { STN_K_TABLEAU = 0,  /* tableau gates, rewrite, frame change */
+       STN_K_BUILD = 1,    /* bond-2 operator blocks, copies, coefficients */
+       STN_K_QR = 2,       /* Householder QR of the compression sweeps and centre moves */
+       STN_K_GEMM = 3,     /* site-pair contractions (R absorb, X V, Q N) */
+       STN_K_GRAM = 4,     /* FP64 Gram X^H X of the truncation */
+       STN_K_EIGEN = 5,    /* FP64 Hermitian eigen-solve of the Gram */
+       STN_K_SELECT = 6,   /* truncation selection, FP64 renormalisation */
+       STN_K_EXPECT = 7,   /* measurement transfer matrices and outcomes */
+       STN_K_COUNT = 8 };
+
+/* Diagnostic profiling.  Bit k of class_mask times every later launch of
+ * kernel class k with HIP events on the context stream and enables the
+ * device counters of algorithmic work (flops and bytes per launch, from the
+ * realised bond dimensions).  class_mask = 0 switches it off.  Resets all
+ * counters; synchronises. */
+stn_status stn_profile(stn_ctx *ctx, unsigned class_mask);
+
+/* Reads (and clears the event list of) the profile: per class the summed
+ * kernel milliseconds, algorithmic flops and bytes, and the number of timed
+ * launches (arrays of STN_K_COUNT entries, any may be NULL), plus the total
+ * number of Jacobi sweeps executed.  Synchronises. */
+stn_status stn_profile_read(stn_ctx *ctx, double *host_ms, double *host_flops,
+                            double *host_bytes, long long *host_launches,
+                            double *host_eig_sweeps);
+
+/* Orthogonality centre site shared by all shots (sites left of it are
+ * left-orthonormal, right of it right-orthonormal). */
+int stn_center(const stn_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STN_H */

@@ -1,0 +1,697 @@
+// libstn host side: context, workspace layout, launch planning and the C ABI
+// declared in include/stn.h.
+//
+// Planning: the x/z bits of the tableau depend on the circuit only (never on
+// the shot), so the host keeps a copy of them, updated by the same gate rules
+// as the device, to know each step's span [l, r] and whether a measurement
+// needs a frame change before launching.  Every result (signs, bits used by
+// the kernels, the MPS, outcomes, probabilities) is computed on the device.
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/stn.h"
+#include "common.h"
+
+namespace {
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------ Pauli conjugation tables
+// For a gate G on k qubits and each local Pauli P = prod i^(x z) X^x Z^z
+// (index x0 | z0<<1 | x1<<2 | z1<<3, qubit 0 = first operand), G^dag P G =
+// i^de P'.  Entry byte = bits(P') | de << 4.  Built from the gate matrices.
+struct Mat {
+  int d;
+  cd a[16];
+  cd &at(int i, int j) { return a[i * d + j]; }
+  cd at(int i, int j) const { return a[i * d + j]; }
+};
+
+Mat mul(const Mat &x, const Mat &y) {
+  Mat r{x.d, {}};
+  for (int i = 0; i < x.d; ++i)
+    for (int j = 0; j < x.d; ++j) {
+      cd s = 0;
+      for (int k = 0; k < x.d; ++k) s += x.at(i, k) * y.at(k, j);
+      r.at(i, j) = s;
+    }
+  return r;
+}
+Mat dag(const Mat &x) {
+  Mat r{x.d, {}};
+  for (int i = 0; i < x.d; ++i)
+    for (int j = 0; j < x.d; ++j) r.at(i, j) = std::conj(x.at(j, i));
+  return r;
+}
+Mat kron(const Mat &x, const Mat &y) {
+  Mat r{x.d * y.d, {}};
+  for (int i = 0; i < x.d; ++i)
+    for (int j = 0; j < x.d; ++j)
+      for (int k = 0; k < y.d; ++k)
+        for (int l = 0; l < y.d; ++l) r.at(i * y.d + k, j * y.d + l) = x.at(i, j) * y.at(k, l);
+  return r;
+}
+Mat pauli1(int x, int z) {
+  const cd I(0, 1);
+  Mat m{2, {}};
+  if (!x && !z) { m.at(0, 0) = 1; m.at(1, 1) = 1; }
+  if (x && !z) { m.at(0, 1) = 1; m.at(1, 0) = 1; }
+  if (!x && z) { m.at(0, 0) = 1; m.at(1, 1) = -1; }
+  if (x && z) { m.at(0, 1) = -I; m.at(1, 0) = I; }   // i X Z = Y
+  return m;
+}
+Mat pauli_idx(int k, int idx) {
+  Mat m = pauli1(idx & 1, (idx >> 1) & 1);
+  if (k == 2) m = kron(m, pauli1((idx >> 2) & 1, (idx >> 3) & 1));
+  return m;
+}
+Mat gate_matrix(int kind) {
+  const double r = 1.0 / std::sqrt(2.0);
+  const cd I(0, 1);
+  Mat m{2, {}};
+  switch (kind) {
+    case STN_GATE_H: m.at(0, 0) = r; m.at(0, 1) = r; m.at(1, 0) = r; m.at(1, 1) = -r; return m;
+    case STN_GATE_S: m.at(0, 0) = 1; m.at(1, 1) = I; return m;
+    case STN_GATE_SDG: m.at(0, 0) = 1; m.at(1, 1) = -I; return m;
+    case STN_GATE_X: return pauli1(1, 0);
+    case STN_GATE_Y: return pauli1(1, 1);
+    case STN_GATE_Z: return pauli1(0, 1);
+    default: break;
+  }
+  Mat u = kind == STN_GATE_CX ? pauli1(1, 0) : kind == STN_GATE_CY ? pauli1(1, 1) : pauli1(0, 1);
+  Mat c{4, {}};
+  c.at(0, 0) = 1; c.at(1, 1) = 1;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) c.at(2 + i, 2 + j) = u.at(i, j);
+  return c;
+}
+bool is_two(int kind) { return kind >= STN_GATE_CX; }
+
+void build_table(int kind, uint8_t *out) {
+  Mat g = gate_matrix(kind);
+  int k = g.d == 4 ? 2 : 1;
+  int cnt = 1 << (2 * k);
+  for (int idx = 0; idx < cnt; ++idx) {
+    Mat m = mul(mul(dag(g), pauli_idx(k, idx)), g);
+    out[idx] = 0xff;
+    for (int o = 0; o < cnt; ++o) {
+      Mat p = pauli_idx(k, o);
+      cd tr = 0;
+      for (int i = 0; i < g.d; ++i)
+        for (int j = 0; j < g.d; ++j) tr += std::conj(p.at(j, i)) * m.at(j, i);
+      tr /= (double)g.d;
+      if (std::abs(tr) > 0.5) {
+        int de = (int)std::lround(std::arg(tr) / (M_PI / 2));
+        de = ((de % 4) + 4) % 4;
+        out[idx] = (uint8_t)(o | (de << 4));
+      }
+    }
+  }
+}
+
+inline int getbit(const uint64_t *v, int j) { return (int)((v[j >> 6] >> (j & 63)) & 1ull); }
+inline void setbit(uint64_t *v, int j, int b) {
+  uint64_t m = 1ull << (j & 63);
+  v[j >> 6] = b ? (v[j >> 6] | m) : (v[j >> 6] & ~m);
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+thread_local Prof *g_prof = nullptr;
+
+hipEvent_t Prof::get() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
+
+struct stn_ctx {
+  stn_config cfg{};
+  int n = 0, S = 0, chi = 0, prec = 0, W = 0, SW = 0;
+  size_t esz = 0;
+  hipStream_t st = nullptr;
+  TabDev tab{};
+  MpsDev mps{};
+  uint64_t *d_pbits = nullptr, *d_psgn = nullptr, *d_snap = nullptr, *d_negmask = nullptr,
+           *d_mmask = nullptr;
+  uint8_t *d_tables = nullptr;
+  c64 *d_ops = nullptr, *d_eops = nullptr;
+  int *d_err = nullptr;
+  int center = 0;
+  std::vector<uint64_t> hx, hz;    // shadow of the shared bits
+  uint8_t tables[9][16];           // per gate kind
+  std::string err;
+  Prof prof;
+  double prof_ms[K_COUNT] = {};
+  long long prof_launches[K_COUNT] = {};
+  ~stn_ctx() {
+    for (auto e : prof.pool) hipEventDestroy(e);
+  }
+};
+
+// Makes the context's recorder visible to the launchers for one API call.
+struct ProfScope {
+  explicit ProfScope(stn_ctx *c) { g_prof = (c && c->prof.mask) ? &c->prof : nullptr; }
+  ~ProfScope() { g_prof = nullptr; }
+};
+
+namespace {
+
+constexpr int kRotChunk = kProgBatch;
+
+struct Layout {
+  size_t total = 0;
+  size_t off(size_t bytes) {
+    size_t o = total;
+    total = align_up(total + bytes);
+    return o;
+  }
+};
+
+int dmax_h(int n, int chi, int b) {
+  int e = b < n - b ? b : n - b;
+  long phys = e >= 30 ? (1L << 30) : (1L << e);
+  return (int)(phys < chi ? phys : chi);
+}
+
+// Computes the workspace layout; when base != nullptr also fills ctx pointers.
+size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> *offs) {
+  const int n = c.n_qubits, S = c.n_shots, chi = c.chi_max;
+  const int W = (n + 63) / 64, SW = (S + 63) / 64;
+  const size_t esz = c.precision == STN_FP64 ? 16 : 8;
+  Layout L;
+  size_t o_x = L.off((size_t)2 * n * W * 8), o_z = L.off((size_t)2 * n * W * 8);
+  size_t o_s = L.off((size_t)2 * n * SW * 8);
+  size_t o_pbits = L.off((size_t)kRotChunk * 2 * W * 8), o_psgn = L.off((size_t)kRotChunk * SW * 8);
+  size_t o_snap = L.off((size_t)(2 * W + SW) * 8);
+  size_t o_neg = L.off((size_t)SW * 8), o_mm = L.off((size_t)SW * 8);
+  size_t o_tab = L.off(64);
+  size_t o_ops = L.off((size_t)n * 8 * sizeof(c64)), o_eops = L.off((size_t)n * 4 * sizeof(c64));
+  size_t o_err = L.off(4);
+  size_t o_work = L.off((size_t)(2 * K_COUNT + 1) * 8);
+  // MPS slots
+  std::vector<int64_t> site_off(n), site_cap(n), ws_off(n), ws_cap(n);
+  int64_t so = 0, wo = 0, Tcap = 1;
+  for (int j = 0; j < n; ++j) {
+    int64_t dl = dmax_h(n, chi, j), dr = dmax_h(n, chi, j + 1);
+    site_cap[j] = dl * 2 * dr;
+    site_off[j] = so;
+    so += site_cap[j] * S;
+    ws_cap[j] = (2 * dl) * 2 * (2 * dr);
+    ws_off[j] = wo;
+    wo += ws_cap[j] * S;
+    Tcap = std::max<int64_t>(Tcap, ws_cap[j]);
+  }
+  int64_t chi_eff = 1;
+  for (int b = 0; b <= n; ++b) chi_eff = std::max<int64_t>(chi_eff, dmax_h(n, chi, b));
+  const int64_t nn = 2 * chi_eff;
+  size_t o_soff = L.off((size_t)n * 8), o_scap = L.off((size_t)n * 8), o_woff = L.off((size_t)n * 8),
+         o_wcap = L.off((size_t)n * 8);
+  size_t o_bond = L.off((size_t)S * (n + 1) * 4), o_wb = L.off((size_t)S * (n + 1) * 4),
+         o_aux = L.off((size_t)S * 8 * 4);
+  size_t o_logp = L.off((size_t)S * 8), o_fid = L.off((size_t)S * 8), o_p0 = L.off((size_t)S * 8),
+         o_nrm = L.off((size_t)S * 8), o_coef = L.off((size_t)S * 2 * sizeof(c64));
+  size_t o_mps = L.off((size_t)so * esz), o_ws = L.off((size_t)wo * esz);
+  size_t o_T = L.off((size_t)Tcap * S * esz), o_R = L.off((size_t)Tcap * S * esz);
+  size_t o_N = L.off((size_t)nn * chi_eff * S * esz), o_Vt = L.off((size_t)nn * chi_eff * S * esz);
+  size_t o_G = L.off((size_t)nn * nn * S * sizeof(c64)), o_V = L.off((size_t)nn * nn * S * sizeof(c64));
+  size_t o_ev = L.off((size_t)nn * S * 8);
+  size_t o_E = L.off((size_t)chi_eff * chi_eff * S * sizeof(c64)),
+         o_F = L.off((size_t)chi_eff * 2 * chi_eff * S * sizeof(c64));
+  if (ctx && base) {
+    ctx->n = n; ctx->S = S; ctx->chi = chi; ctx->prec = c.precision; ctx->W = W; ctx->SW = SW;
+    ctx->esz = esz;
+    ctx->tab = TabDev{n, W, SW, (uint64_t *)(base + o_x), (uint64_t *)(base + o_z), (uint64_t *)(base + o_s)};
+    ctx->d_pbits = (uint64_t *)(base + o_pbits);
+    ctx->d_psgn = (uint64_t *)(base + o_psgn);
+    ctx->d_snap = (uint64_t *)(base + o_snap);
+    ctx->d_negmask = (uint64_t *)(base + o_neg);
+    ctx->d_mmask = (uint64_t *)(base + o_mm);
+    ctx->d_tables = (uint8_t *)(base + o_tab);
+    ctx->d_ops = (c64 *)(base + o_ops);
+    ctx->d_eops = (c64 *)(base + o_eops);
+    ctx->d_err = (int *)(base + o_err);
+    MpsDev &m = ctx->mps;
+    m.n = n; m.S = S; m.chi = chi;
+    m.site_off = (int64_t *)(base + o_soff); m.site_cap = (int64_t *)(base + o_scap);
+    m.ws_off = (int64_t *)(base + o_woff); m.ws_cap = (int64_t *)(base + o_wcap);
+    m.mps = base + o_mps; m.ws = base + o_ws;
+    m.bond = (int *)(base + o_bond); m.wb = (int *)(base + o_wb); m.aux = (int *)(base + o_aux);
+    m.T = base + o_T; m.T_cap = Tcap;
+    m.R = base + o_R; m.R_cap = Tcap;
+    m.N = base + o_N; m.N_cap = nn * chi_eff;
+    m.Vt = base + o_Vt; m.Vt_cap = nn * chi_eff;
+    m.G = (c64 *)(base + o_G); m.G_cap = nn * nn;
+    m.V = (c64 *)(base + o_V); m.V_cap = nn * nn;
+    m.ev = (double *)(base + o_ev); m.ev_cap = nn;
+    m.E = (c64 *)(base + o_E); m.E_cap = chi_eff * chi_eff;
+    m.F = (c64 *)(base + o_F); m.F_cap = chi_eff * 2 * chi_eff;
+    m.logp = (double *)(base + o_logp); m.fid = (double *)(base + o_fid);
+    m.p0 = (double *)(base + o_p0); m.nrm = (double *)(base + o_nrm);
+    m.coef = (c64 *)(base + o_coef);
+    m.err = ctx->d_err;
+    m.eps_cut = c.eps_cut;
+    m.prof = 0;
+    m.work = (double *)(base + o_work);
+    if (offs) {
+      offs->clear();
+      for (auto *v : {&site_off, &site_cap, &ws_off, &ws_cap}) offs->insert(offs->end(), v->begin(), v->end());
+    }
+  }
+  return L.total;
+}
+
+bool valid(const stn_config *c) {
+  return c && c->n_qubits >= 1 && c->n_qubits <= 1024 && c->n_shots >= 1 && c->chi_max >= 1 &&
+         c->chi_max <= 512 && (c->precision == STN_FP64 || c->precision == STN_FP32) &&
+         c->eps_cut >= 0 && c->eps_cut < 1;
+}
+
+stn_status fail(stn_ctx *ctx, stn_status s, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+stn_status check_launch(stn_ctx *ctx) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  return STN_OK;
+}
+
+stn_status sync_status(stn_ctx *ctx) {
+  hipError_t e = hipStreamSynchronize(ctx->st);
+  if (e != hipSuccess) return fail(ctx, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  int flags = 0;
+  e = hipMemcpy(&flags, ctx->d_err, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(ctx, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  if (flags & STN_ERR_ZEROPROB) return fail(ctx, STN_EZEROPROB, "forced outcome with probability 0");
+  if (flags & STN_ERR_NUMERIC) return fail(ctx, STN_ENUMERIC, "non-finite value in the state or the angles");
+  if (flags & STN_ERR_PHASE) return fail(ctx, STN_ENUMERIC, "tableau row product with an imaginary phase");
+  if (flags & STN_ERR_EIGEN) return fail(ctx, STN_ENUMERIC, "Jacobi eigen-solve did not converge");
+  return STN_OK;
+}
+
+// ----------------------------------------------------- host shadow updates
+void shadow_product(stn_ctx *c, const RowProg &p, uint64_t *ox, uint64_t *oz) {
+  for (int w = 0; w < c->W; ++w) { ox[w] = 0; oz[w] = 0; }
+  for (int i = 0; i < p.nsrc; ++i)
+    for (int w = 0; w < c->W; ++w) {
+      ox[w] ^= c->hx[(size_t)p.src[i] * c->W + w];
+      oz[w] ^= c->hz[(size_t)p.src[i] * c->W + w];
+    }
+}
+
+// Row programs of one gate: each generator row of the support becomes
+// i^e0 * product of old rows (G^dag g G expressed in generators).
+int gate_programs(stn_ctx *c, const stn_gate &g, RowProg *out) {
+  const int k = is_two(g.kind) ? 2 : 1;
+  const int q[2] = {g.q0, g.q1};
+  int np = 0;
+  for (int i = 0; i < k; ++i)
+    for (int which = 0; which < 2; ++which) {            // 0: X_q, 1: Z_q
+      int idx = which == 0 ? (1 << (2 * i)) : (2 << (2 * i));
+      uint8_t ent = c->tables[g.kind][idx];
+      int bits = ent & 15, de = ent >> 4;
+      RowProg p{};
+      p.dst = (int16_t)(which == 0 ? q[i] : c->n + q[i]);
+      p.e0 = (int16_t)de;
+      for (int s = 0; s < k; ++s) {
+        int x = (bits >> (2 * s)) & 1, z = (bits >> (2 * s + 1)) & 1;
+        if (x) p.src[p.nsrc++] = (int16_t)q[s];
+        if (z) p.src[p.nsrc++] = (int16_t)(c->n + q[s]);
+        p.e0 = (int16_t)((p.e0 + x * z) & 3);
+      }
+      out[np++] = p;
+    }
+  return np;
+}
+
+void shadow_apply(stn_ctx *c, const RowProg *progs, int np) {
+  std::vector<uint64_t> nx(np * c->W), nz(np * c->W);
+  for (int i = 0; i < np; ++i) shadow_product(c, progs[i], &nx[i * c->W], &nz[i * c->W]);
+  for (int i = 0; i < np; ++i)
+    for (int w = 0; w < c->W; ++w) {
+      c->hx[(size_t)progs[i].dst * c->W + w] = nx[i * c->W + w];
+      c->hz[(size_t)progs[i].dst * c->W + w] = nz[i * c->W + w];
+    }
+}
+
+// Bits of the frame change V = D_k prod C-Q_j H_k applied to every row.
+void shadow_frame(stn_ctx *c, const uint64_t *px, const uint64_t *pz, int k) {
+  const int alpha_i = getbit(pz, k);
+  for (int row = 0; row < 2 * c->n; ++row) {
+    uint64_t *rx = &c->hx[(size_t)row * c->W], *rz = &c->hz[(size_t)row * c->W];
+    if (alpha_i) setbit(rz, k, getbit(rz, k) ^ getbit(rx, k));
+    for (int j = 0; j < c->n; ++j) {
+      if (j == k || !(getbit(px, j) | getbit(pz, j))) continue;
+      int kind = getbit(px, j) ? (getbit(pz, j) ? STN_GATE_CY : STN_GATE_CX) : STN_GATE_CZ;
+      int idx = getbit(rx, k) | (getbit(rz, k) << 1) | (getbit(rx, j) << 2) | (getbit(rz, j) << 3);
+      uint8_t ent = c->tables[kind][idx];
+      setbit(rx, k, ent & 1); setbit(rz, k, (ent >> 1) & 1);
+      setbit(rx, j, (ent >> 2) & 1); setbit(rz, j, (ent >> 3) & 1);
+    }
+    int idx = getbit(rx, k) | (getbit(rz, k) << 1);
+    uint8_t ent = c->tables[STN_GATE_H][idx];
+    setbit(rx, k, ent & 1); setbit(rz, k, (ent >> 1) & 1);
+  }
+}
+
+void span_of(stn_ctx *c, const uint64_t *px, const uint64_t *pz, int *l, int *r, int *pivot) {
+  *l = -1; *r = -1; *pivot = -1;
+  for (int j = 0; j < c->n; ++j) {
+    if (getbit(px, j) | getbit(pz, j)) {
+      if (*l < 0) *l = j;
+      *r = j;
+    }
+    if (*pivot < 0 && getbit(px, j)) *pivot = j;
+  }
+}
+
+// ----------------------------------------------------- MPS step dispatch
+template <typename T>
+void move_center_into(stn_ctx *c, int l, int r) {
+  while (c->center < l) { mps_move_right<T>(c->mps, c->center, c->st); c->center++; }
+  while (c->center > r) { mps_move_left<T>(c->mps, c->center, c->st); c->center--; }
+}
+
+// Two-term step over [l, r] with ops/coef already on the device.
+template <typename T>
+void two_term(stn_ctx *c, int l, int r, bool unitary) {
+  if (l == r) {
+    if (!unitary) move_center_into<T>(c, l, l);
+    mps_apply_single<T>(c->mps, l, c->d_ops, c->st);
+    if (!unitary) mps_normalize_site<T>(c->mps, l, c->st);
+    return;
+  }
+  move_center_into<T>(c, l, r);
+  mps_build<T>(c->mps, l, r, c->d_ops, c->st);
+  mps_sweep_lr<T>(c->mps, l, r, c->st);
+  mps_sweep_rl<T>(c->mps, l, r, c->st);
+  c->center = l;
+}
+
+template <typename T>
+stn_status rotate_impl(stn_ctx *c, const int32_t *qs, int n_rot, const double *theta, int64_t stride) {
+  for (int r0 = 0; r0 < n_rot; r0 += kRotChunk) {
+    const int cnt = std::min(kRotChunk, n_rot - r0);
+    ProgBatch b{};
+    b.n = cnt;
+    for (int i = 0; i < cnt; ++i) {
+      RowProg p{};
+      p.dst = -1;
+      for (int k = 0; k < 3; ++k) {
+        int q = qs[(r0 + i) * 3 + k];
+        if (q >= 0) p.src[p.nsrc++] = (int16_t)(c->n + q);
+      }
+      b.p[i] = p;
+    }
+    launch_tab_products(c->tab, b, c->d_pbits, c->d_psgn, c->d_err, c->st);
+    for (int i = 0; i < cnt; ++i) {
+      std::vector<uint64_t> px(c->W), pz(c->W);
+      shadow_product(c, b.p[i], px.data(), pz.data());
+      int l, r, piv;
+      span_of(c, px.data(), pz.data(), &l, &r, &piv);
+      if (l < 0) return fail(c, STN_EINVAL, "rotation Pauli is the identity");
+      const uint64_t *bits = c->d_pbits + (size_t)i * 2 * c->W;
+      launch_ops_rotation(bits, c->W, l, r, c->d_ops, c->st);
+      launch_coef_rotation(c->d_psgn + (size_t)i * c->SW, c->S, theta, stride, r0 + i, c->mps.coef,
+                           c->d_err, c->st);
+      two_term<T>(c, l, r, true);
+    }
+  }
+  return check_launch(c);
+}
+
+template <typename T>
+stn_status measure_impl(stn_ctx *c, const int32_t *qs, int n_meas, int reset, const double *u,
+                        const uint8_t *forced, uint8_t *out, double *prob) {
+  for (int i = 0; i < n_meas; ++i) {
+    const int q = qs[i];
+    const int row = c->n + q;
+    std::vector<uint64_t> px(c->hx.begin() + (size_t)row * c->W, c->hx.begin() + (size_t)(row + 1) * c->W);
+    std::vector<uint64_t> pz(c->hz.begin() + (size_t)row * c->W, c->hz.begin() + (size_t)(row + 1) * c->W);
+    int l, r, piv;
+    span_of(c, px.data(), pz.data(), &l, &r, &piv);
+    launch_tab_snapshot(c->tab, row, c->d_snap, c->st);
+    launch_ops_measure(c->d_snap, c->W, l, r, piv, c->d_ops, c->d_eops, c->st);
+    move_center_into<T>(c, l, l);
+    mps_expect<T>(c->mps, l, r, c->d_eops, c->st);
+    launch_outcome(c->mps, c->d_snap + 2 * c->W, piv, r + 1, u, forced, n_meas, i, out, prob,
+                   c->d_negmask, c->d_mmask, c->st);
+    two_term<T>(c, l, r, false);
+    if (piv >= 0) {
+      launch_tab_frame(c->tab, c->d_snap, c->d_negmask, c->d_tables, c->st);
+      shadow_frame(c, px.data(), pz.data(), piv);
+    }
+    if (reset) launch_tab_flip(c->tab, row, c->d_mmask, c->st);
+  }
+  return check_launch(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stn_workspace_bytes(const stn_config *cfg) {
+  if (!valid(cfg)) return 0;
+  return plan(*cfg, nullptr, nullptr, nullptr);
+}
+
+stn_status stn_init(stn_ctx **out, const stn_config *cfg, void *ws, size_t bytes) {
+  if (!out || !valid(cfg) || !ws) return STN_EINVAL;
+  if (((uintptr_t)ws & 255) != 0) return STN_EINVAL;
+  size_t need = plan(*cfg, nullptr, nullptr, nullptr);
+  if (bytes < need) return STN_ENOMEM;
+  stn_ctx *c = new stn_ctx();
+  c->cfg = *cfg;
+  c->st = (hipStream_t)cfg->stream;
+  std::vector<int64_t> offs;
+  plan(*cfg, c, (char *)ws, &offs);
+  for (int k = 0; k <= STN_GATE_CZ; ++k) build_table(k, c->tables[k]);
+  // frame tables: [0] H, [1] CX, [2] CY, [3] CZ
+  uint8_t ft[64];
+  memcpy(ft, c->tables[STN_GATE_H], 16);
+  memcpy(ft + 16, c->tables[STN_GATE_CX], 16);
+  memcpy(ft + 32, c->tables[STN_GATE_CY], 16);
+  memcpy(ft + 48, c->tables[STN_GATE_CZ], 16);
+  const int n = c->n;
+  c->hx.assign((size_t)2 * n * c->W, 0);
+  c->hz.assign((size_t)2 * n * c->W, 0);
+  for (int j = 0; j < n; ++j) {
+    setbit(&c->hx[(size_t)j * c->W], j, 1);
+    setbit(&c->hz[(size_t)(n + j) * c->W], j, 1);
+  }
+  hipError_t e = hipSuccess;
+  e = e ? e : hipMemcpyAsync(c->tab.x, c->hx.data(), c->hx.size() * 8, hipMemcpyHostToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(c->tab.z, c->hz.data(), c->hz.size() * 8, hipMemcpyHostToDevice, c->st);
+  e = e ? e : hipMemsetAsync(c->tab.s, 0, (size_t)2 * n * c->SW * 8, c->st);
+  e = e ? e : hipMemcpyAsync(c->d_tables, ft, 64, hipMemcpyHostToDevice, c->st);
+  {
+    int64_t *dst[4] = {c->mps.site_off, c->mps.site_cap, c->mps.ws_off, c->mps.ws_cap};
+    for (int a = 0; a < 4; ++a)
+      e = e ? e : hipMemcpyAsync(dst[a], offs.data() + (size_t)a * n, (size_t)n * 8, hipMemcpyHostToDevice, c->st);
+  }
+  e = e ? e : hipMemsetAsync(c->d_err, 0, 4, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) {
+    delete c;
+    return STN_EDEVICE;
+  }
+  if (c->prec == STN_FP64) mps_init<double>(c->mps, c->st);
+  else mps_init<float>(c->mps, c->st);
+  if (hipGetLastError() != hipSuccess) {
+    delete c;
+    return STN_EDEVICE;
+  }
+  c->center = 0;
+  *out = c;
+  return STN_OK;
+}
+
+void stn_free(stn_ctx *ctx) { delete ctx; }
+
+const char *stn_last_error(const stn_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int stn_center(const stn_ctx *ctx) { return ctx ? ctx->center : -1; }
+
+stn_status stn_clifford(stn_ctx *c, const stn_gate *gates, int n_gates, const uint64_t *noise) {
+  ProfScope ps_(c);
+  if (!c || n_gates < 0 || (n_gates > 0 && !gates)) return fail(c, STN_EINVAL, "bad arguments");
+  for (int i = 0; i < n_gates; ++i) {
+    const stn_gate &g = gates[i];
+    if (g.kind < 0 || g.kind > STN_GATE_CZ || g.q0 < 0 || g.q0 >= c->n)
+      return fail(c, STN_EINVAL, "bad gate kind or qubit");
+    if (is_two(g.kind) && (g.q1 < 0 || g.q1 >= c->n || g.q1 == g.q0))
+      return fail(c, STN_EINVAL, "bad two-qubit gate operands");
+  }
+  // split into layers of gates on disjoint qubits, preserving order
+  std::vector<int> used(c->n, -1);
+  int layer = 0;
+  ProgBatch b{};
+  std::vector<RowProg> pending;
+  auto flush = [&]() {
+    if (b.ngates == 0) return;
+    launch_tab_gates(c->tab, b, c->d_err, c->st);
+    shadow_apply(c, b.p, b.n);
+    b = ProgBatch{};
+  };
+  for (int i = 0; i < n_gates; ++i) {
+    const stn_gate &g = gates[i];
+    bool clash = used[g.q0] == layer || (is_two(g.kind) && used[g.q1] == layer);
+    if (clash) { flush(); layer++; }
+    RowProg progs[4];
+    int np = gate_programs(c, g, progs);
+    if (b.n + np > kProgBatch) flush();
+    b.first[b.ngates] = b.n;
+    for (int k = 0; k < np; ++k) b.p[b.n++] = progs[k];
+    b.ngates++;
+    b.first[b.ngates] = b.n;
+    used[g.q0] = layer;
+    if (is_two(g.kind)) used[g.q1] = layer;
+  }
+  flush();
+  if (noise) launch_tab_noise(c->tab, noise, c->st);
+  return check_launch(c);
+}
+
+stn_status stn_rotate(stn_ctx *c, const int32_t *qs, int n_rot, const double *theta, int64_t stride) {
+  ProfScope ps_(c);
+  if (!c || n_rot < 0 || (n_rot > 0 && (!qs || !theta)) || stride < 0)
+    return fail(c, STN_EINVAL, "bad arguments");
+  for (int i = 0; i < n_rot; ++i) {
+    int cnt = 0;
+    for (int k = 0; k < 3; ++k) {
+      int q = qs[i * 3 + k];
+      if (q < -1 || q >= c->n) return fail(c, STN_EINVAL, "bad rotation qubit");
+      if (q >= 0) {
+        for (int k2 = 0; k2 < k; ++k2)
+          if (qs[i * 3 + k2] == q) return fail(c, STN_EINVAL, "repeated rotation qubit");
+        cnt++;
+      }
+    }
+    if (cnt < 2) return fail(c, STN_EINVAL, "rotation needs at least two qubits");
+  }
+  return c->prec == STN_FP64 ? rotate_impl<double>(c, qs, n_rot, theta, stride)
+                             : rotate_impl<float>(c, qs, n_rot, theta, stride);
+}
+
+stn_status stn_measure(stn_ctx *c, const int32_t *qs, int n_meas, int reset, const double *u,
+                       const uint8_t *forced, uint8_t *out, double *prob) {
+  ProfScope ps_(c);
+  if (!c || n_meas < 0 || (n_meas > 0 && !qs) || (!u && !forced)) return fail(c, STN_EINVAL, "bad arguments");
+  for (int i = 0; i < n_meas; ++i)
+    if (qs[i] < 0 || qs[i] >= c->n) return fail(c, STN_EINVAL, "bad measured qubit");
+  return c->prec == STN_FP64 ? measure_impl<double>(c, qs, n_meas, reset, u, forced, out, prob)
+                             : measure_impl<float>(c, qs, n_meas, reset, u, forced, out, prob);
+}
+
+stn_status stn_profile(stn_ctx *c, unsigned class_mask) {
+  if (!c) return STN_EINVAL;
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  c->prof.mask = class_mask;
+  c->prof.recs.clear();
+  c->prof.used = 0;
+  for (int k = 0; k < K_COUNT; ++k) { c->prof_ms[k] = 0; c->prof_launches[k] = 0; }
+  c->mps.prof = class_mask ? 1 : 0;
+  hipError_t e = hipMemsetAsync(c->mps.work, 0, (size_t)(2 * K_COUNT + 1) * 8, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
+}
+
+stn_status stn_profile_read(stn_ctx *c, double *ms, double *flops, double *bytes, long long *launches,
+                            double *eig_sweeps) {
+  if (!c) return STN_EINVAL;
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  for (auto &r : c->prof.recs) {
+    float t = 0;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) c->prof_ms[r.cls] += t;
+    c->prof_launches[r.cls]++;
+  }
+  c->prof.recs.clear();
+  c->prof.used = 0;
+  double w[2 * K_COUNT + 1];
+  hipError_t e = hipMemcpy(w, c->mps.work, sizeof(w), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
+  for (int k = 0; k < K_COUNT; ++k) {
+    if (ms) ms[k] = c->prof_ms[k];
+    if (flops) flops[k] = w[2 * k];
+    if (bytes) bytes[k] = w[2 * k + 1];
+    if (launches) launches[k] = c->prof_launches[k];
+  }
+  if (eig_sweeps) *eig_sweeps = w[2 * K_COUNT];
+  return STN_OK;
+}
+
+stn_status stn_sync(stn_ctx *c) {
+  if (!c) return STN_EINVAL;
+  return sync_status(c);
+}
+
+stn_status stn_logprob(stn_ctx *c, double *logp, double *terr) {
+  if (!c) return STN_EINVAL;
+  hipError_t e = hipSuccess;
+  if (logp) e = hipMemcpyAsync(logp, c->mps.logp, (size_t)c->S * 8, hipMemcpyDeviceToDevice, c->st);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
+  if (terr) {
+    std::vector<double> f(c->S);
+    e = hipMemcpyAsync(f.data(), c->mps.fid, (size_t)c->S * 8, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
+    for (auto &v : f) v = 1.0 - v;
+    e = hipMemcpy(terr, f.data(), (size_t)c->S * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
+  }
+  return sync_status(c);
+}
+
+stn_status stn_get_tableau(stn_ctx *c, uint64_t *hx, uint64_t *hz, uint64_t *hs) {
+  if (!c) return STN_EINVAL;
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  size_t nb = (size_t)2 * c->n * c->W * 8, ns = (size_t)2 * c->n * c->SW * 8;
+  hipError_t e = hipSuccess;
+  if (hx) e = hipMemcpy(hx, c->tab.x, nb, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && hz) e = hipMemcpy(hz, c->tab.z, nb, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && hs) e = hipMemcpy(hs, c->tab.s, ns, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
+}
+
+stn_status stn_get_bonds(stn_ctx *c, int32_t *hb) {
+  if (!c || !hb) return STN_EINVAL;
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  hipError_t e = hipMemcpy(hb, c->mps.bond, (size_t)c->S * (c->n + 1) * 4, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
+}
+
+stn_status stn_get_site(stn_ctx *c, int shot, int site, void *buf, size_t bytes, int *dl, int *dr) {
+  if (!c || !buf || shot < 0 || shot >= c->S || site < 0 || site >= c->n) return STN_EINVAL;
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  int b[2];
+  hipError_t e = hipMemcpy(b, c->mps.bond + (size_t)shot * (c->n + 1) + site, 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
+  size_t need = (size_t)b[0] * 2 * b[1] * c->esz;
+  if (bytes < need) return fail(c, STN_EINVAL, "buffer too small");
+  int64_t off, cap;
+  e = hipMemcpy(&off, c->mps.site_off + site, 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&cap, c->mps.site_cap + site, 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(buf, (char *)c->mps.mps + (off + (int64_t)shot * cap) * c->esz, need, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
+  if (dl) *dl = b[0];
+  if (dr) *dr = b[1];
+  return STN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,315 @@
+"""ctypes binding of libstn (include/stn.h).  Argument marshalling only:
+every step of the simulation runs in the library's HIP kernels; PyTorch
+provides device memory and the stream.  There is no CPU fallback: importing
+works anywhere, but creating a Simulator without the built library or
+without a GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstn.so")
+
+STN_FP64, STN_FP32 = 0, 1
+GATE_KIND = {"H": 0, "S": 1, "SDG": 2, "X": 3, "Y": 4, "Z": 5, "CX": 6, "CY": 7, "CZ": 8}
+STATUS = {0: "STN_OK", -1: "STN_EINVAL", -2: "STN_ENOMEM", -3: "STN_EDEVICE",
+          -4: "STN_EZEROPROB", -5: "STN_ENUMERIC", -6: "STN_ESTATE"}
+DEFAULT_EPS = {STN_FP64: 1e-16, STN_FP32: 1e-14}
+
+
+class STNError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class StnConfig(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int), ("n_shots", ctypes.c_int), ("chi_max", ctypes.c_int),
+                ("precision", ctypes.c_int), ("eps_cut", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class StnGate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32)]
+
+
+_lib = None
+EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn_clifford",
+           "stn_rotate", "stn_measure", "stn_logprob", "stn_sync", "stn_get_tableau",
+           "stn_get_bonds", "stn_get_site", "stn_center", "stn_profile", "stn_profile_read"]
+K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect"]
+
+
+def load(path: str = LIB_PATH):
+    """Load libstn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2605_29514_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    lib.stn_workspace_bytes.restype = ctypes.c_size_t
+    lib.stn_workspace_bytes.argtypes = [ctypes.POINTER(StnConfig)]
+    lib.stn_init.restype = i32
+    lib.stn_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(StnConfig), vp, ctypes.c_size_t]
+    lib.stn_free.restype = None
+    lib.stn_free.argtypes = [vp]
+    lib.stn_last_error.restype = ctypes.c_char_p
+    lib.stn_last_error.argtypes = [vp]
+    lib.stn_clifford.restype = i32
+    lib.stn_clifford.argtypes = [vp, ctypes.POINTER(StnGate), i32, vp]
+    lib.stn_rotate.restype = i32
+    lib.stn_rotate.argtypes = [vp, vp, i32, vp, i64]
+    lib.stn_measure.restype = i32
+    lib.stn_measure.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
+    lib.stn_logprob.restype = i32
+    lib.stn_logprob.argtypes = [vp, vp, vp]
+    lib.stn_sync.restype = i32
+    lib.stn_sync.argtypes = [vp]
+    lib.stn_get_tableau.restype = i32
+    lib.stn_get_tableau.argtypes = [vp, vp, vp, vp]
+    lib.stn_get_bonds.restype = i32
+    lib.stn_get_bonds.argtypes = [vp, vp]
+    lib.stn_get_site.restype = i32
+    lib.stn_get_site.argtypes = [vp, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(i32),
+                                 ctypes.POINTER(i32)]
+    lib.stn_center.restype = i32
+    lib.stn_center.argtypes = [vp]
+    lib.stn_profile.restype = i32
+    lib.stn_profile.argtypes = [vp, ctypes.c_uint]
+    lib.stn_profile_read.restype = i32
+    lib.stn_profile_read.argtypes = [vp, vp, vp, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def pack_shots(mask: np.ndarray) -> np.ndarray:
+    """bool [S, n] -> uint64 sign words [n, ceil(S/64)] (bit s%64 of word s//64)."""
+    S, n = mask.shape
+    SW = (S + 63) // 64
+    pad = np.zeros((SW * 64, n), dtype=np.uint64)
+    pad[:S] = mask
+    b = pad.reshape(SW, 64, n) << np.arange(64, dtype=np.uint64)[None, :, None]
+    return np.bitwise_or.reduce(b, axis=1).T.copy()
+
+
+def unpack_shots(words: np.ndarray, S: int) -> np.ndarray:
+    """uint64 [..., SW] -> bool [..., S]."""
+    bits = (words[..., :, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)
+    return bits.reshape(*words.shape[:-1], -1)[..., :S].astype(bool)
+
+
+def unpack_bits(words: np.ndarray, n: int) -> np.ndarray:
+    return unpack_shots(words, n)
+
+
+class Simulator:
+    """One libstn context on a CUDA (HIP) device with a torch-owned workspace."""
+
+    def __init__(self, n_qubits: int, n_shots: int, chi_max: int, precision: str = "fp32",
+                 eps_cut: Optional[float] = None, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libstn needs a GPU; no device is visible")
+        self.lib = load()
+        self.device = torch.device(device)
+        self.prec = STN_FP64 if precision == "fp64" else STN_FP32
+        self.n, self.S, self.chi = n_qubits, n_shots, chi_max
+        self.eps_cut = DEFAULT_EPS[self.prec] if eps_cut is None else eps_cut
+        self.stream = torch.cuda.current_stream(self.device)
+        self.cfg = StnConfig(n_qubits, n_shots, chi_max, self.prec, self.eps_cut,
+                             ctypes.c_void_p(self.stream.cuda_stream))
+        nbytes = self.lib.stn_workspace_bytes(ctypes.byref(self.cfg))
+        if nbytes == 0:
+            raise STNError(-1, "invalid configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.ctx = ctypes.c_void_p()
+        st = self.lib.stn_init(ctypes.byref(self.ctx), ctypes.byref(self.cfg),
+                               ctypes.c_void_p(aligned), nbytes)
+        if st != 0:
+            raise STNError(st, "stn_init failed")
+        self.W = (n_qubits + 63) // 64
+        self.SW = (n_shots + 63) // 64
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value and getattr(self, "lib", None) is not None:
+            self.lib.stn_free(ctx)
+            self.ctx = None
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, st: int):
+        if st != 0:
+            raise STNError(st, self.lib.stn_last_error(self.ctx).decode())
+
+    def _dev(self, arr, dtype):
+        t = self.torch
+        if isinstance(arr, t.Tensor):
+            return arr.to(self.device, dtype).contiguous()
+        return t.as_tensor(np.ascontiguousarray(arr), dtype=dtype, device=self.device)
+
+    # ------------------------------------------------------------ the ABI
+    def clifford(self, gates, noise=None):
+        """gates: list of (name, q0, q1); noise: device int64 tensor [2, n, SW] or None."""
+        arr = (StnGate * max(1, len(gates)))()
+        for i, (name, q0, q1) in enumerate(gates):
+            arr[i] = StnGate(GATE_KIND[name], int(q0), int(q1))
+        ptr = None if noise is None else ctypes.c_void_p(noise.data_ptr())
+        self._check(self.lib.stn_clifford(self.ctx, arr, len(gates), ptr))
+
+    def rotate(self, qubits: np.ndarray, theta, stride: int):
+        q = np.ascontiguousarray(qubits, dtype=np.int32)
+        self._check(self.lib.stn_rotate(self.ctx, q.ctypes.data_as(ctypes.c_void_p), len(q),
+                                        ctypes.c_void_p(theta.data_ptr()), int(stride)))
+
+    def measure(self, qubits: np.ndarray, reset: bool, u=None, forced=None, out=None, prob=None):
+        q = np.ascontiguousarray(qubits, dtype=np.int32)
+        M = len(q)
+        t = self.torch
+        if out is None:
+            out = t.empty((self.S, M), dtype=t.uint8, device=self.device)
+        if prob is None:
+            prob = t.empty((self.S, M), dtype=t.float64, device=self.device)
+        up = None if u is None else ctypes.c_void_p(u.data_ptr())
+        fp = None if forced is None else ctypes.c_void_p(forced.data_ptr())
+        self._check(self.lib.stn_measure(self.ctx, q.ctypes.data_as(ctypes.c_void_p), M, int(bool(reset)),
+                                         up, fp, ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(prob.data_ptr())))
+        return out, prob
+
+    def logprob(self):
+        t = self.torch
+        lp = t.empty(self.S, dtype=t.float64, device=self.device)
+        te = t.empty(self.S, dtype=t.float64, device=self.device)
+        self._check(self.lib.stn_logprob(self.ctx, ctypes.c_void_p(lp.data_ptr()),
+                                         ctypes.c_void_p(te.data_ptr())))
+        return lp, te
+
+    def sync(self):
+        self._check(self.lib.stn_sync(self.ctx))
+
+    def tableau(self):
+        """(x [2n, n] bool, z [2n, n] bool, sign [2n, S] bool)."""
+        n = self.n
+        hx = np.zeros((2 * n, self.W), np.uint64)
+        hz = np.zeros((2 * n, self.W), np.uint64)
+        hs = np.zeros((2 * n, self.SW), np.uint64)
+        self._check(self.lib.stn_get_tableau(self.ctx, hx.ctypes.data_as(ctypes.c_void_p),
+                                             hz.ctypes.data_as(ctypes.c_void_p),
+                                             hs.ctypes.data_as(ctypes.c_void_p)))
+        return unpack_bits(hx, n), unpack_bits(hz, n), unpack_shots(hs, self.S)
+
+    def bonds(self) -> np.ndarray:
+        b = np.zeros((self.S, self.n + 1), np.int32)
+        self._check(self.lib.stn_get_bonds(self.ctx, b.ctypes.data_as(ctypes.c_void_p)))
+        return b
+
+    def site(self, shot: int, j: int) -> np.ndarray:
+        cap = self.chi * 2 * self.chi
+        ctype = np.complex128 if self.prec == STN_FP64 else np.complex64
+        buf = np.zeros(cap, ctype)
+        dl, dr = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.stn_get_site(self.ctx, shot, j, buf.ctypes.data_as(ctypes.c_void_p),
+                                          buf.nbytes, ctypes.byref(dl), ctypes.byref(dr)))
+        return buf[: dl.value * 2 * dr.value].reshape(dl.value, 2, dr.value).astype(np.complex128)
+
+    def mps(self, shot: int):
+        return [self.site(shot, j) for j in range(self.n)]
+
+    def center(self) -> int:
+        return self.lib.stn_center(self.ctx)
+
+    def profile(self, classes=None):
+        """Start profiling the named kernel classes (None: all; []: stop)."""
+        if classes is None:
+            classes = K_CLASSES
+        mask = 0
+        for c in classes:
+            mask |= 1 << K_CLASSES.index(c)
+        self._check(self.lib.stn_profile(self.ctx, mask))
+
+    def profile_read(self) -> dict:
+        K = len(K_CLASSES)
+        ms, fl, by = np.zeros(K), np.zeros(K), np.zeros(K)
+        ln = np.zeros(K, np.int64)
+        sw = np.zeros(1)
+        self._check(self.lib.stn_profile_read(self.ctx, *(a.ctypes.data_as(ctypes.c_void_p) for a in (ms, fl, by, ln, sw))))
+        out = {c: {"ms": float(ms[i]), "flops": float(fl[i]), "bytes": float(by[i]),
+                   "launches": int(ln[i])} for i, c in enumerate(K_CLASSES)}
+        out["eigen_sweeps"] = float(sw[0])
+        return out
+
+
+# ----------------------------------------------------------------- circuits
+def prepare(circ, device="cuda:0", forced: Optional[np.ndarray] = None):
+    """Uploads every per-shot input of a workload Circuit to the device once
+    (noise sign words, angles, measurement uniforms or forced outcomes).
+    forced: uint8 [S, n_measurements] or None."""
+    import torch
+    dev = torch.device(device)
+    ops = []
+    mi = 0
+    for op in circ.ops:
+        k = op["op"]
+        if k == "gates":
+            ops.append(("gates", [(g[0], g[1], g[2]) for g in op["gates"]]))
+        elif k == "noise":
+            words = np.stack([pack_shots(op["x"]), pack_shots(op["z"])])
+            ops.append(("noise", torch.from_numpy(words.view(np.int64)).to(dev)))
+        elif k == "rotate":
+            th = np.ascontiguousarray(op["theta"], dtype=np.float64)
+            shared = bool(np.all(th == th[:1]))
+            tdev = torch.from_numpy(th[0].copy() if shared else th).to(dev)
+            ops.append(("rotate", np.ascontiguousarray(op["paulis"], np.int32), tdev,
+                        0 if shared else th.shape[1]))
+        elif k == "measure":
+            M = len(op["qubits"])
+            u = torch.from_numpy(np.ascontiguousarray(op["u"], np.float64)).to(dev)
+            f = None
+            if forced is not None:
+                f = torch.from_numpy(np.ascontiguousarray(forced[:, mi:mi + M], np.uint8)).to(dev)
+            ops.append(("measure", np.ascontiguousarray(op["qubits"], np.int32), bool(op["reset"]), u, f))
+            mi += M
+    return ops
+
+
+def run_prepared(sim: Simulator, ops, start: int = 0, stop: Optional[int] = None, records=None):
+    """Runs prepared ops [start, stop) on a Simulator; returns the list of
+    (outcomes, prob) device tensors of the measurement ops run."""
+    res = [] if records is None else records
+    for op in ops[start:stop]:
+        k = op[0]
+        if k == "gates":
+            sim.clifford(op[1])
+        elif k == "noise":
+            sim.clifford([], op[1])
+        elif k == "rotate":
+            sim.rotate(op[1], op[2], op[3])
+        elif k == "measure":
+            res.append(sim.measure(op[1], op[2], u=None if op[4] is not None else op[3], forced=op[4]))
+    return res
+
+
+def run_circuit(circ, chi_max: int, precision: str = "fp32", eps_cut: Optional[float] = None,
+                device: str = "cuda:0", forced: Optional[np.ndarray] = None, sim: Optional[Simulator] = None):
+    """Simulates every shot of a workload Circuit on the GPU.  Returns a dict
+    with records [S, M] uint8, prob [S, M], logp [S], trunc_err [S] (numpy)
+    and the Simulator (for tableau / MPS inspection)."""
+    if sim is None:
+        sim = Simulator(circ.n, circ.n_shots, chi_max, precision, eps_cut, device)
+    ops = prepare(circ, device, forced)
+    res = run_prepared(sim, ops)
+    lp, te = sim.logprob()
+    import torch
+    rec = torch.cat([r[0] for r in res], dim=1).cpu().numpy() if res else np.zeros((circ.n_shots, 0), np.uint8)
+    prob = torch.cat([r[1] for r in res], dim=1).cpu().numpy() if res else np.zeros((circ.n_shots, 0))
+    return {"records": rec, "prob": prob, "logp": lp.cpu().numpy(), "trunc_err": te.cpu().numpy(),
+            "sim": sim}
