@@ -1,0 +1,236 @@
+"""Throughput benchmark of the STN crosstalk step on one MI355X.
+
+Workload: rotated surface code d=5 memory-Z experiment (49 qubits, 5
+syndrome rounds), ZZ crosstalk after each of the 4 CNOT layers on the 80
+nearest-neighbour pairs (theta ~ U[0.02, 0.10] per coupling) and the 72
+next-nearest pairs (own draw, halved), depolarising p = 1e-3 (Table I
+ratios), chi_max = 256, FP32 complex contractions with FP64 Gram, eigen-solve
+and norms, 1024 shots batched.  All inputs are seeded and synthetic and are
+resident in device memory before the timed region starts.
+
+A step is one syndrome-extraction round over every shot: Clifford layers and
+noise (tableau), 608 crosstalk rotations (rewrite, bond-2 update, QR sweep,
+Gram/eigen truncation) and 24 ancilla measurements (projection, frame change,
+reset); the last round also reads out the data qubits.  --warmup W rounds run
+untimed first (they are the circuit's own first rounds), then --steps K rounds
+are timed.
+
+Prints one JSON line.  value = (shots x rotations in the timed rounds) / time.
+roofline: the kernel class with the largest time in the timed region, its
+algorithmic work (counted on the device from the realised bond dimensions)
+over its own launch time (HIP events on the library stream).
+cpu_baseline: the FP64 oracle timed on the host cores over a bounded sample
+of the same rounds (see --cpu-seconds).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp32_vector_TFs": 157.3,
+    "fp64_vector_TFs": 78.6,
+    "fp32_mfma_TFs": 157.3,
+    "fp64_mfma_TFs": 78.6,
+}
+# which unit bounds each kernel class of the current kernels
+CLASS_BOUND = {
+    "eigen": ("alu", "fp64_vector_TFs"),    # FP64 Jacobi rotations on vector ALUs
+    "gram": ("alu", "fp64_vector_TFs"),     # FP64-accumulated FMA tiles
+    "expect": ("alu", "fp64_vector_TFs"),
+    "qr": ("alu", None),                    # precision-dependent
+    "gemm": ("alu", None),
+    "build": ("hbm", "hbm_GBs"),
+    "select": ("hbm", "hbm_GBs"),
+    "tableau": ("hbm", "hbm_GBs"),
+}
+
+
+def split_rounds(ops):
+    """Indices [start, stop) of each syndrome round in prepared ops; a round
+    ends with an ancilla measurement (the final data readout joins the last)."""
+    bounds, start = [], 0
+    for i, op in enumerate(ops):
+        if op[0] == "measure" and op[2]:          # reset=True: ancilla round end
+            bounds.append([start, i + 1])
+            start = i + 1
+    if start < len(ops):
+        bounds[-1][1] = len(ops)
+    return bounds
+
+
+def rotations_in(circ_ops, lo, hi):
+    return sum(len(o[1]) for o in circ_ops[lo:hi] if o[0] == "rotate")
+
+
+# ----------------------------------------------------------------- CPU leg
+def _oracle_worker(args):
+    name, shot, shots_total, warm_lo, warm_hi, t_lo, t_hi, budget, chi, eps = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import stn as ostn
+    from paper_2605_29514_amd import workload
+    circ, _ = workload.make_config(name, n_shots=shots_total)
+    st = ostn.Shot(circ.n, chi, eps)
+    done = 0
+    t0 = None
+    for oi, op in enumerate(circ.ops):
+        if oi == t_lo:
+            t0 = time.perf_counter()
+        if t0 is not None and (oi >= t_hi or time.perf_counter() - t0 > budget):
+            break
+        k = op["op"]
+        if k == "gates":
+            for g in op["gates"]:
+                st.gate(g[0], [g[1], g[2]])
+        elif k == "noise":
+            st.pauli_noise(op["x"][shot], op["z"][shot])
+        elif k == "rotate":
+            for ri, qs in enumerate(op["paulis"]):
+                st.rotate([int(q) for q in qs], float(op["theta"][shot, ri]))
+                if t0 is not None:
+                    done += 1
+                    if time.perf_counter() - t0 > budget:
+                        break
+        elif k == "measure":
+            for mj, q in enumerate(op["qubits"]):
+                st.measure(int(q), float(op["u"][shot, mj]), None, bool(op["reset"]))
+    el = time.perf_counter() - t0 if t0 is not None else 0.0
+    return done, el
+
+
+def cpu_baseline(name, circ, ops_bounds, t_lo_round, t_hi_round, chi, eps, budget, cores):
+    """Oracle rotations/s over the same rounds, one shot per core (BLAS 1 thread)."""
+    # map prepared-op rounds to circuit-op indices (prepared ops mirror circuit ops 1:1)
+    t_lo, t_hi = ops_bounds[t_lo_round][0], ops_bounds[t_hi_round - 1][1]
+    args = [(name, s, circ.n_shots, 0, t_lo, t_lo, t_hi, budget, chi, eps) for s in range(cores)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, args)
+    wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    return {"value": done / busy if busy > 0 else 0.0, "unit": "rotations/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{cores} shots (one per core, FP64 numpy, BLAS 1 thread) replayed to the timed "
+                      f"rounds, then up to {budget:.0f} s of rotations each; {done} rotations in {busy:.1f} s "
+                      f"(wall incl. replay {wall:.1f} s)"}
+
+
+# ----------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--config", default="d5_nnn_chi256")
+    ap.add_argument("--shots", type=int, default=None, help="override the shot count (testing only)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-all", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(shots would shard across GPUs with one final gather).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_29514_amd import stn, workload
+
+    cfg = dict(workload.CONFIGS[args.config])
+    over = {} if args.shots is None else {"n_shots": args.shots}
+    circ, opts = workload.make_config(args.config, **over)
+    chi, prec = opts["chi_max"], opts["precision"]
+    eps = stn.DEFAULT_EPS[stn.STN_FP64 if prec == "fp64" else stn.STN_FP32]
+    dev = "cuda:0"
+    print(f"# building inputs: {args.config} shots={circ.n_shots}", file=sys.stderr, flush=True)
+    sim = stn.Simulator(circ.n, circ.n_shots, chi, prec, eps, dev)
+    ops = stn.prepare(circ, dev)
+    rounds = split_rounds(ops)
+    W, K = args.warmup, args.steps
+    if W + K > len(rounds):
+        print(f"warmup + steps exceeds the {len(rounds)} rounds of the circuit", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.synchronize()
+    for r in range(W):
+        t = time.perf_counter()
+        stn.run_prepared(sim, ops, *rounds[r])
+        sim.sync()
+        print(f"# warmup round {r + 1}: {time.perf_counter() - t:.2f} s, max bond "
+              f"{int(sim.bonds().max())}", file=sys.stderr, flush=True)
+    # dominant-class timing: all classes when asked, else the expected heaviest
+    sim.profile(None if args.profile_all else ["eigen", "qr", "gemm", "gram"])
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(sim.stream)
+    for r in range(W, W + K):
+        stn.run_prepared(sim, ops, *rounds[r])
+        print(f"# timed round {r + 1} enqueued at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    ev1.record(sim.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    sim.sync()
+    prof = sim.profile_read()
+    lo, hi = rounds[W][0], rounds[W + K - 1][1]
+    n_rot = rotations_in(ops, lo, hi) * circ.n_shots
+    bonds = sim.bonds()
+    value = n_rot / (ms / 1e3)
+    # dominant kernel class by measured time
+    classes = [c for c in stn.K_CLASSES if prof[c]["launches"] > 0]
+    dom = max(classes, key=lambda c: prof[c]["ms"]) if classes else None
+    roof = None
+    if dom:
+        bound, peak_key = CLASS_BOUND[dom]
+        if peak_key is None:
+            peak_key = "fp64_vector_TFs" if prec == "fp64" else "fp32_vector_TFs"
+        d = prof[dom]
+        per_launch_ms = d["ms"] / d["launches"]
+        if bound == "hbm":
+            achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9
+            unit = "GB/s"
+        else:
+            achieved = d["flops"] / (d["ms"] / 1e3) / 1e12
+            unit = "TFLOP/s"
+        peak = PEAKS[peak_key]
+        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None, "kernel_class": dom,
+                "launches": d["launches"], "avg_launch_ms": per_launch_ms,
+                "share_of_step_time": d["ms"] / ms if ms > 0 else None}
+    cpu = None
+    if not args.no_cpu:
+        cores = min(os.cpu_count() or 1, 16)
+        print(f"# cpu baseline on {cores} cores", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.config, circ, rounds, W, W + K, chi, 1e-16 if prec == "fp64" else 1e-14,
+                           args.cpu_seconds, cores)
+    out = {
+        "metric": "crosstalk rotations/sec (shots x gates) at d=5, chi=256",
+        "value": value, "unit": "rotations/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 contractions + f64 gram/eigen/norms" if prec == "fp32" else "c128",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: rotated surface code d={cfg['d']} memory-Z, "
+                               f"{circ.n} qubits, rounds {W + 1}-{W + K} of {cfg['rounds']}",
+                   "shots": circ.n_shots, "chi_max": chi, "rotations_timed": n_rot,
+                   "max_bond_after": int(bonds.max()), "mean_bond_after": float(bonds.mean()),
+                   "wall_s": wall, "eigen_sweeps": prof["eigen_sweeps"],
+                   "class_ms": {c: prof[c]["ms"] for c in classes}},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -184,6 +184,18 @@ stn_status stn_profile_read(stn_ctx *ctx, double *host_ms, double *host_flops,
                             double *host_bytes, long long *host_launches,
                             double *host_eig_sweeps);
 
+/* Overwrite one MPS site tensor of one shot from the host (synchronises):
+ * host_buf holds dl*2*dr complex elements in the layout of stn_get_site; the
+ * shot's bonds site and site+1 become dl and dr.  The caller keeps the
+ * neighbouring sites consistent and the orthogonality centre as declared by
+ * stn_set_center (used to restore a checkpointed state).  STN_EINVAL when a
+ * bond exceeds min(chi_max, 2^min(b, n-b)). */
+stn_status stn_set_site(stn_ctx *ctx, int shot, int site, const void *host_buf,
+                        int dl, int dr);
+
+/* Declare the orthogonality centre of the state held (after stn_set_site). */
+stn_status stn_set_center(stn_ctx *ctx, int center);
+
 /* Orthogonality centre site shared by all shots (sites left of it are
  * left-orthonormal, right of it right-orthonormal). */
 int stn_center(const stn_ctx *ctx);

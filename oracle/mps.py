@@ -74,6 +74,11 @@ class MPS:
         self.center = 0
         self.fidelity = 1.0                    # prod over cuts of (1 - w)
         self.discarded = []                    # per-cut discarded weight w
+        # conditioning of the cuts where chi_max binds: s_k^2 / (s_k^2 - s_{k+1}^2)
+        # for the last kept value k (inf for an exact tie).  Eq. 8 keeps the
+        # largest values but leaves ties at the cut open; a large value means the
+        # kept subspace is ill-conditioned.
+        self.max_cut_sensitivity = 0.0
 
     # ------------------------------------------------------------------ basics
     def bonds(self):
@@ -188,6 +193,10 @@ class MPS:
             u, s, vh = svd(t.reshape(dl, 2 * dr))
             k = keep_count(s, self.chi_max, self.eps_cut)
             tot = float(np.sum(s.astype(np.float64) ** 2))
+            if k < len(s) and s[k] ** 2 > self.eps_cut * tot:
+                gap = float(s[k - 1] ** 2 - s[k] ** 2)
+                sens = float(s[k - 1] ** 2) / gap if gap > 0 else float("inf")
+                self.max_cut_sensitivity = max(self.max_cut_sensitivity, sens)
             w = float(np.sum(s[k:].astype(np.float64) ** 2)) / tot if tot > 0 else 0.0
             self.discarded.append(w)
             self.fidelity *= (1.0 - w)

@@ -694,4 +694,29 @@ stn_status stn_get_site(stn_ctx *c, int shot, int site, void *buf, size_t bytes,
   return STN_OK;
 }
 
+stn_status stn_set_site(stn_ctx *c, int shot, int site, const void *buf, int dl, int dr) {
+  if (!c || !buf || shot < 0 || shot >= c->S || site < 0 || site >= c->n) return STN_EINVAL;
+  if (dl < 1 || dr < 1 || dl > dmax_h(c->n, c->chi, site) || dr > dmax_h(c->n, c->chi, site + 1) ||
+      (site == 0 && dl != 1) || (site == c->n - 1 && dr != 1))
+    return fail(c, STN_EINVAL, "site shape exceeds the bond caps");
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  int64_t off, cap;
+  hipError_t e = hipMemcpy(&off, c->mps.site_off + site, 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&cap, c->mps.site_cap + site, 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy((char *)c->mps.mps + (off + (int64_t)shot * cap) * c->esz, buf,
+                  (size_t)dl * 2 * dr * c->esz, hipMemcpyHostToDevice);
+  int b[2] = {dl, dr};
+  if (e == hipSuccess)
+    e = hipMemcpy(c->mps.bond + (size_t)shot * (c->n + 1) + site, b, 8, hipMemcpyHostToDevice);
+  return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
+}
+
+stn_status stn_set_center(stn_ctx *c, int center) {
+  if (!c || center < 0 || center >= c->n) return STN_EINVAL;
+  c->center = center;
+  return STN_OK;
+}
+
 }  // extern "C"

@@ -153,11 +153,15 @@ __device__ void qr_block(int m, int nc, cplx<T> *A, cplx<T> *Qd, int qt, cplx<T>
   const int p = m < nc ? m : nc;
   const int tid = threadIdx.x;
   for (int k = 0; k < p; ++k) {
+    // Norms and the phase of x0 are formed from double copies: squaring a
+    // float below ~1e-19 lands in the denormal range, and an inexact |x0|
+    // would leave x0/|x0| off the unit circle, so H = I - 2 v v^H would stop
+    // being unitary.
     double part = 0;
-    for (int i = k + tid; i < m; i += TB) part += (double)norm2(A[(size_t)i * nc + k]);
+    for (int i = k + tid; i < m; i += TB) part += norm2(cvt<double>(A[(size_t)i * nc + k]));
     double xn2 = block_sum(part);
     C x0 = A[(size_t)k * nc + k];
-    double ax0 = sqrt((double)norm2(x0));
+    double ax0 = hypot((double)x0.x, (double)x0.y);
     double xn = sqrt(xn2);
     c64 ph = ax0 > 0 ? mk<double>(x0.x / ax0, x0.y / ax0) : mk<double>(1, 0);
     c64 alpha = mk<double>(-ph.x * xn, -ph.y * xn);
@@ -235,7 +239,7 @@ __device__ void qr_block(int m, int nc, cplx<T> *A, cplx<T> *Qd, int qt, cplx<T>
 // with c = |c| e^{i phi} and R the real symmetric Jacobi rotation.
 __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int *err,
                              int *pos, double *pc, double *ps, c64 *pe, int *pp, int *pq,
-                             int *sweeps_out) {
+                             int *sweeps_out, double abs_tol, double rel_tol) {
   const int tid = threadIdx.x;
   const int P = nn + (nn & 1);
   if (sweeps_out && tid == 0) *sweeps_out = 0;
@@ -243,14 +247,15 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
   for (int i = tid; i < P; i += TB) pos[i] = i;
   __syncthreads();
   // The Gram matrix is positive semi-definite, so its trace bounds every
-  // eigenvalue and is invariant under the rotations: entries below 1e-16 tr
-  // are left alone and the sweep stops once the largest off-diagonal entry is
-  // below 1e-15 tr (eigenvalue errors at the FP64 rounding level of the Gram).
+  // eigenvalue and is invariant under the rotations.  An entry G_pq is
+  // negligible when |G_pq| <= max(abs_tol tr, rel_tol sqrt(G_pp G_qq)): the
+  // relative part keeps small kept eigenvalues from mixing with the (near)
+  // null space, the absolute floor stops at the rounding level of the Gram.
   double trp = 0;
   for (int i = tid; i < nn; i += TB) trp += G[(size_t)i * nn + i].x;
   const double tr = block_sum(trp);
-  const double skip = 1e-16 * tr, stop = 1e-15 * tr;
-  const int max_sweeps = 40;
+  const double afl = abs_tol * tr;
+  const int max_sweeps = 60;
   bool converged = nn <= 1 || !(tr > 0);
   int sweeps_done = 0;
   double last_off = 0;
@@ -265,7 +270,7 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
           c64 c = G[(size_t)p * nn + q];
           double h = sqrt(norm2(c));
           double a = G[(size_t)p * nn + p].x, b = G[(size_t)q * nn + q].x;
-          if (h > skip) {
+          if (h > afl && h > rel_tol * sqrt(fabs(a * b))) {
             eph = mk<double>(c.x / h, c.y / h);
             double tau = (b - a) / (2 * h);
             double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1 + tau * tau));
@@ -311,12 +316,18 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
       }
       __syncthreads();
     }
-    double off = 0;
-    for (int e = tid; e < nn * nn; e += TB)
-      if (e / nn != e % nn) off = fmax(off, sqrt(norm2(G[e])));
+    double off = 0, viol = 0;
+    for (int e = tid; e < nn * nn; e += TB) {
+      const int p = e / nn, q = e % nn;
+      if (p == q) continue;
+      const double h = sqrt(norm2(G[e]));
+      off = fmax(off, h);
+      if (h > afl && h > rel_tol * sqrt(fabs(G[(size_t)p * nn + p].x * G[(size_t)q * nn + q].x))) viol = 1;
+    }
     off = block_max(off);
+    viol = block_max(viol);
     last_off = off;
-    converged = off <= stop;
+    converged = viol == 0;
     sweeps_done = sweep + 1;
   }
   if (sweeps_out && tid == 0) *sweeps_out = sweeps_done;
@@ -482,7 +493,8 @@ __global__ void k_eig(MpsDev m, int j) {
   // eigenvectors are accumulated in V and written sorted back into G
   __shared__ int sweeps;
   jacobi_block(nn, m.G + s * m.G_cap, m.V + s * m.V_cap, m.ev + s * m.ev_cap, m.G + s * m.G_cap,
-               m.err, pos, pc, ps, pe, pp, pq, &sweeps);
+               m.err, pos, pc, ps, pe, pp, pq, &sweeps,
+               sizeof(T) == 8 ? 1e-18 : 1e-16, sizeof(T) == 8 ? 1e-15 : 1e-13);
   // algorithmic work: a Hermitian eigendecomposition with vectors, ~9 n^3 real
   // flops (x4 complex); bytes: read G, write eigenvalues and vectors.
   if (threadIdx.x == 0) add_work(m, K_EIGEN, 36.0 * nn * nn * (double)nn, 16.0 * 2 * nn * nn + 8.0 * nn);
@@ -517,6 +529,7 @@ __global__ void k_select(MpsDev m, int j) {
     if (!(tot == tot) || isinf(tot)) atomicOr(m.err, STN_ERR_NUMERIC);
     kk = k;
     auxp(m, s)[2] = k;
+    auxp(m, s)[3] = w[j];          // L, read by the Q N product while wb[j] changes
   }
   __syncthreads();
   const int k = kk;
@@ -553,7 +566,7 @@ template <typename T>
 __global__ void k_xgemm(MpsDev m, int j) {
   const int s = blockIdx.z;
   int *w = wbd(m, s);
-  const int M = 2 * w[j - 1], L = w[j], k = auxp(m, s)[2];
+  const int M = 2 * w[j - 1], L = auxp(m, s)[3], k = auxp(m, s)[2];
   if (blockIdx.y * GT < M && blockIdx.x * GT < k)
     gemm_tile<T, T, T, T>(M, k, L, wslot<T>(m, j - 1, s), L, 0, scr<T>(m.N, m.N_cap, s), k, 0,
                           scr<T>(m.T, m.T_cap, s), k, blockIdx.y, blockIdx.x);
@@ -573,7 +586,7 @@ __global__ void k_finish(MpsDev m, int l) {
   const int cnt = w[l] * 2 * w[l + 1];
   const cplx<T> *X = scr<T>(m.T, m.T_cap, s);
   double part = 0;
-  for (int e = threadIdx.x; e < cnt; e += TB) part += (double)norm2(X[e]);
+  for (int e = threadIdx.x; e < cnt; e += TB) part += norm2(cvt<double>(X[e]));
   double n2 = block_sum(part);
   if (!(n2 > 0) || isinf(n2)) {
     if (threadIdx.x == 0) atomicOr(m.err, STN_ERR_NUMERIC);
@@ -595,7 +608,7 @@ __global__ void k_normalize(MpsDev m, int site) {
   const int cnt = bnd(m, s)[site] * 2 * bnd(m, s)[site + 1];
   cplx<T> *A = slot<T>(m, site, s);
   double part = 0;
-  for (int e = threadIdx.x; e < cnt; e += TB) part += (double)norm2(A[e]);
+  for (int e = threadIdx.x; e < cnt; e += TB) part += norm2(cvt<double>(A[e]));
   double n2 = block_sum(part);
   if (!(n2 > 0) || isinf(n2)) {
     if (threadIdx.x == 0) atomicOr(m.err, STN_ERR_NUMERIC);
@@ -612,7 +625,7 @@ __global__ void k_sitenorm(MpsDev m, int site) {
   const int cnt = bnd(m, s)[site] * 2 * bnd(m, s)[site + 1];
   const cplx<T> *A = slot<T>(m, site, s);
   double part = 0;
-  for (int e = threadIdx.x; e < cnt; e += TB) part += (double)norm2(A[e]);
+  for (int e = threadIdx.x; e < cnt; e += TB) part += norm2(cvt<double>(A[e]));
   double n2 = block_sum(part);
   if (threadIdx.x == 0) m.nrm[s] = n2;
 }

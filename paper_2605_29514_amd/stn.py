@@ -40,7 +40,8 @@ class StnGate(ctypes.Structure):
 _lib = None
 EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn_clifford",
            "stn_rotate", "stn_measure", "stn_logprob", "stn_sync", "stn_get_tableau",
-           "stn_get_bonds", "stn_get_site", "stn_center", "stn_profile", "stn_profile_read"]
+           "stn_get_bonds", "stn_get_site", "stn_center", "stn_profile", "stn_profile_read",
+           "stn_set_site", "stn_set_center"]
 K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect"]
 
 
@@ -80,6 +81,10 @@ def load(path: str = LIB_PATH):
                                  ctypes.POINTER(i32)]
     lib.stn_center.restype = i32
     lib.stn_center.argtypes = [vp]
+    lib.stn_set_site.restype = i32
+    lib.stn_set_site.argtypes = [vp, i32, i32, vp, i32, i32]
+    lib.stn_set_center.restype = i32
+    lib.stn_set_center.argtypes = [vp, i32]
     lib.stn_profile.restype = i32
     lib.stn_profile.argtypes = [vp, ctypes.c_uint]
     lib.stn_profile_read.restype = i32
@@ -112,7 +117,7 @@ class Simulator:
     """One libstn context on a CUDA (HIP) device with a torch-owned workspace."""
 
     def __init__(self, n_qubits: int, n_shots: int, chi_max: int, precision: str = "fp32",
-                 eps_cut: Optional[float] = None, device: str = "cuda:0"):
+                 eps_cut: Optional[float] = None, device: str = "cuda:0", poison: bool = False):
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -129,6 +134,8 @@ class Simulator:
         if nbytes == 0:
             raise STNError(-1, "invalid configuration")
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        if poison:              # testing aid: NaN bytes expose reads of unwritten workspace
+            self.workspace.fill_(0xFF)
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
         self.ctx = ctypes.c_void_p()
@@ -223,6 +230,17 @@ class Simulator:
 
     def mps(self, shot: int):
         return [self.site(shot, j) for j in range(self.n)]
+
+    def set_site(self, shot: int, j: int, t: np.ndarray):
+        ctype = np.complex128 if self.prec == STN_FP64 else np.complex64
+        a = np.ascontiguousarray(t, dtype=ctype)
+        self._check(self.lib.stn_set_site(self.ctx, shot, j, a.ctypes.data_as(ctypes.c_void_p),
+                                          a.shape[0], a.shape[2]))
+
+    def set_mps(self, shot: int, tensors, center: int):
+        for j, t in enumerate(tensors):
+            self.set_site(shot, j, t)
+        self._check(self.lib.stn_set_center(self.ctx, center))
 
     def center(self) -> int:
         return self.lib.stn_center(self.ctx)

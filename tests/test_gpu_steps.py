@@ -1,0 +1,119 @@
+"""Single-step GPU parity from identical random states (needs an MI355X).
+
+A random canonical MPS is loaded into both the GPU context (stn_set_site)
+and the oracle, a random Clifford frame is applied to both, then ONE step
+runs on each side: a crosstalk rotation (Sec. IV.A, Eq. 4) or a forced Z
+measurement (Sec. IV.A).  The resulting states must agree (fidelity) and the
+measurement probability must agree, for FP64 and FP32, with and without a
+binding chi_max.  This isolates the kernels of one step from trajectory
+effects.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import stn as ostn
+from oracle.mps import MPS
+
+pytestmark = pytest.mark.gpu
+
+FID = {"fp64": 1e-11, "fp32": 2e-6}
+PT = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+def random_state(n, chi, rng):
+    m = MPS(n, 1 << 20, 0.0)
+    dims = [1] + [min(chi, 2 ** min(j, n - j)) for j in range(1, n)] + [1]
+    for j in range(n):
+        m.A[j] = rng.normal(size=(dims[j], 2, dims[j + 1])) + 1j * rng.normal(size=(dims[j], 2, dims[j + 1]))
+    m.center = 0
+    m.move_center(n - 1)
+    c = int(rng.integers(n))
+    m.move_center(c)
+    m.normalize()
+    return m
+
+
+def random_frame(n, rng, k):
+    gates = []
+    for _ in range(k):
+        g = ["H", "S", "CX", "CZ"][rng.integers(4)]
+        if g in ("H", "S"):
+            gates.append((g, int(rng.integers(n)), -1))
+        else:
+            a, b = rng.choice(n, 2, replace=False)
+            gates.append((g, int(a), int(b)))
+    return gates
+
+
+def one_case(B, prec, seed, n=10, chi_state=8, chi_max=8, kind="rotate"):
+    import torch
+    rng = np.random.default_rng(seed)
+    eps = 1e-16 if prec == "fp64" else 1e-14
+    state = random_state(n, min(chi_state, chi_max), rng)
+    gates = random_frame(n, rng, int(rng.integers(0, 25)))
+    sim = B.Simulator(n, 1, chi_max, prec, eps)
+    sim.set_mps(0, state.A, state.center)
+    sim.clifford(gates)
+    st = ostn.Shot(n, chi_max, eps)
+    st.mps = state.copy()
+    st.mps.chi_max, st.mps.eps_cut = chi_max, eps
+    for g in gates:
+        st.gate(g[0], [g[1], g[2]])
+    info = {}
+    if kind == "rotate":
+        k = int(rng.integers(2, 4))
+        qs = [int(q) for q in rng.choice(n, k, replace=False)] + [-1] * (3 - k)
+        th = float(rng.uniform(-1, 1))
+        sim.rotate(np.array([qs], np.int32), torch.tensor([th], dtype=torch.float64, device="cuda:0"), 0)
+        st.rotate(qs, th)
+        info = {"qubits": qs, "theta": th}
+    else:
+        q = int(rng.integers(n))
+        p = st.tab.rz(q)
+        ev = st.mps.expect(ostn.site_ops(p)).real / st.mps.norm2()
+        p0 = 0.5 * (1 + p.sign() * ev)
+        m = 0 if p0 >= 0.5 else 1
+        reset = bool(rng.random() < 0.5)
+        st.measure(q, None, m, reset)
+        out, prob = sim.measure(np.array([q], np.int32), reset,
+                                forced=torch.tensor([[m]], dtype=torch.uint8, device="cuda:0"))
+        info = {"qubit": q, "p": st.res.prob[-1], "gpu_p": float(prob.cpu()[0, 0]),
+                "pivot": bool(p.x.any())}
+    g = MPS(n)
+    g.A = sim.mps(0)
+    f = 1 - abs(g.overlap(st.mps)) / np.sqrt(abs(g.overlap(g)) * abs(st.mps.overlap(st.mps)))
+    info["fid_deficit"] = f
+    info["sens"] = st.mps.max_cut_sensitivity
+    return info
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_29514_amd import stn as binding
+    binding.load()
+    return binding
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["rotate", "measure"])
+@pytest.mark.parametrize("chi_max", [8, 4])
+def test_single_steps(B, prec, kind, chi_max):
+    bad = []
+    for seed in range(24):
+        info = one_case(B, prec, seed, chi_max=chi_max, kind=kind)
+        if info["sens"] > (1e6 if prec == "fp64" else 30.0):
+            continue                      # ill-conditioned cut: kept subspace not defined to precision
+        ok = info["fid_deficit"] <= FID[prec]
+        if kind == "measure":
+            ok = ok and abs(info["gpu_p"] - info["p"]) <= PT[prec] * info["p"]
+        if not ok:
+            bad.append((seed, info))
+    for b in bad:
+        print("FAIL", b, flush=True)
+    sys.stdout.flush()
+    assert not bad
