@@ -56,6 +56,22 @@ CLASS_BOUND = {
 }
 
 
+def measured_traffic(kernel_class):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 PMC
+    summary (profiles/traffic_*.json), or None when no summary matches the
+    class or the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2605_29514_amd", "csrc", "mps.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        with open(path) as f:
+            t = json.load(f)
+        if t.get("kernel_class") == kernel_class and t.get("source_sha256_16") == sha:
+            return float(t["traffic_bytes_per_launch"])
+    return None
+
+
 def split_rounds(ops):
     """Indices [start, stop) of each syndrome round in prepared ops; a round
     ends with an ancilla measurement (the final data readout joins the last)."""
@@ -138,7 +154,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-all", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (scales HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "read_bytes": n, "write_bytes": n}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(shots would shard across GPUs with one final gather).", file=sys.stderr)
@@ -205,8 +233,10 @@ def main():
             unit = "TFLOP/s"
         peak = PEAKS[peak_key]
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "kernel_class": dom,
+                "frac": achieved / peak, "traffic": measured_traffic(dom), "kernel_class": dom,
                 "launches": d["launches"], "avg_launch_ms": per_launch_ms,
+                "algorithmic_flops_per_launch": d["flops"] / d["launches"],
+                "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
                 "share_of_step_time": d["ms"] / ms if ms > 0 else None}
     cpu = None
     if not args.no_cpu:

@@ -505,6 +505,14 @@ stn_status stn_init(stn_ctx **out, const stn_config *cfg, void *ws, size_t bytes
     delete c;
     return STN_EDEVICE;
   }
+  {
+    int max_rows = 4 * c->chi;                           // QR rows of a doubled tensor
+    hipError_t pe = c->prec == STN_FP64 ? mps_prepare<double>(max_rows) : mps_prepare<float>(max_rows);
+    if (pe != hipSuccess) {
+      delete c;
+      return STN_EDEVICE;
+    }
+  }
   if (c->prec == STN_FP64) mps_init<double>(c->mps, c->st);
   else mps_init<float>(c->mps, c->st);
   if (hipGetLastError() != hipSuccess) {

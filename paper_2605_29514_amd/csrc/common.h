@@ -62,9 +62,9 @@ extern thread_local Prof *g_prof;
     Prof *p_ = g_prof;                                                                 \
     bool on_ = p_ && (p_->mask >> (cls) & 1u);                                         \
     hipEvent_t a_ = nullptr, b_ = nullptr;                                             \
-    if (on_) { a_ = p_->get(); hipEventRecord(a_, st); }                               \
+    if (on_) { a_ = p_->get(); (void)hipEventRecord(a_, st); }                               \
     hipLaunchKernelGGL(kern, grid, block, lds, st, __VA_ARGS__);                       \
-    if (on_) { b_ = p_->get(); hipEventRecord(b_, st); p_->recs.push_back({cls, a_, b_}); } \
+    if (on_) { b_ = p_->get(); (void)hipEventRecord(b_, st); p_->recs.push_back({cls, a_, b_}); } \
   } while (0)
 
 // ---------------------------------------------------------------- tableau
@@ -132,6 +132,7 @@ struct MpsDev {
 // Site operator table of one two-term step: for site j in [l, r],
 // ops[(j - l) * 8 + {0..3}] = O1 (row-major 2x2), [+4..7] = O2.
 
+template <typename T> hipError_t mps_prepare(int max_rows);
 template <typename T> void mps_init(const MpsDev &m, hipStream_t st);
 template <typename T> void mps_apply_single(const MpsDev &m, int site, const c64 *d_ops, hipStream_t st);
 template <typename T> void mps_build(const MpsDev &m, int l, int r, const c64 *d_ops, hipStream_t st);

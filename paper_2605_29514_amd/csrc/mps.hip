@@ -25,6 +25,7 @@ namespace {
 constexpr int TB = 256;          // threads per block
 constexpr int GT = 32;           // GEMM tile (GT x GT outputs)
 constexpr int GK = 16;           // GEMM k-step
+constexpr int kEigLdsN = 32;     // Jacobi in LDS up to this order (2 x 16 KB)
 
 template <typename T>
 struct Acc { using type = T; };
@@ -78,6 +79,17 @@ __device__ void gemm_tile(int M, int N, int K, const cplx<TA> *A, int lda, int o
     }
 }
 
+// All tiles of one shot's product, strided over the blocks given to it:
+// grids are sized from a per-shot block budget, not from the largest
+// possible bonds, so early (small-bond) steps do not launch empty tiles.
+template <typename TA, typename TB_, typename TC, typename ACC>
+__device__ void gemm_all(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
+                         const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc) {
+  const int ntm = (M + GT - 1) / GT, ntn = (N + GT - 1) / GT;
+  for (int t = blockIdx.x; t < ntm * ntn; t += gridDim.x)
+    gemm_tile<TA, TB_, TC, ACC>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, t / ntn, t % ntn);
+}
+
 template <typename T>
 __device__ inline cplx<T> *slot(const MpsDev &m, int j, int s) {
   return reinterpret_cast<cplx<T> *>(m.mps) + m.site_off[j] + (int64_t)s * m.site_cap[j];
@@ -101,7 +113,7 @@ __device__ inline void add_work(const MpsDev &m, int cls, double flops, double b
     atomicAdd(&m.work[2 * cls + 1], bytes);
   }
 }
-__device__ inline bool first_block() { return blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0; }
+__device__ inline bool first_block() { return blockIdx.x == 0 && threadIdx.x == 0; }
 __device__ inline double gemm_flops(double M, double N, double K) { return 8.0 * M * N * K; }
 // Householder QR of an m x n complex matrix with p = min(m, n) reflectors,
 // R plus the explicit m x p Q: 4x the real counts 2mnp - (m+n)p^2 + 2p^3/3
@@ -229,6 +241,25 @@ __device__ void qr_block(int m, int nc, cplx<T> *A, cplx<T> *Qd, int qt, cplx<T>
       Qd[e] = q;
   }
   __syncthreads();
+}
+
+// QR of the m x nc matrix at A (global).  When it fits, the matrix is first
+// copied to LDS (after the reflector scratch) so the column sweeps run at
+// LDS rather than L2 bandwidth.  lds_rows: rows the scratch was sized for.
+constexpr size_t kQrLdsMat = 16 * 1024;
+template <typename T>
+__device__ void qr_dispatch(int rows, int cols, cplx<T> *A, cplx<T> *Qd, int qt, cplx<T> *Rd,
+                            char *lds, int lds_rows) {
+  c64 *vs = reinterpret_cast<c64 *>(lds);
+  double *vd = reinterpret_cast<double *>(vs + lds_rows);
+  cplx<T> *Al = reinterpret_cast<cplx<T> *>(vd + 2 * lds_rows);
+  if ((size_t)rows * cols * sizeof(cplx<T>) <= kQrLdsMat) {
+    for (int e = threadIdx.x; e < rows * cols; e += TB) Al[e] = A[e];
+    __syncthreads();
+    qr_block<T>(rows, cols, Al, Qd, qt, Rd, vs, vd);
+  } else {
+    qr_block<T>(rows, cols, A, Qd, qt, Rd, vs, vd);
+  }
 }
 
 // ------------------------------------------------ Jacobi eigen-solve (FP64)
@@ -371,10 +402,9 @@ template <typename T>
 __global__ void k_apply1(MpsDev m, int site, const c64 *ops) {
   const int s = blockIdx.y;
   const int dl = bnd(m, s)[site], dr = bnd(m, s)[site + 1];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= dl * dr) return;
-  const int a = e / dr, c = e % dr;
   cplx<T> *A = slot<T>(m, site, s);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < dl * dr; e += gridDim.x * blockDim.x) {
+  const int a = e / dr, c = e % dr;
   c64 x0 = cvt<double>(A[(size_t)(a * 2 + 0) * dr + c]);
   c64 x1 = cvt<double>(A[(size_t)(a * 2 + 1) * dr + c]);
   c64 ca = m.coef[2 * s], cb = m.coef[2 * s + 1];
@@ -383,6 +413,7 @@ __global__ void k_apply1(MpsDev m, int site, const c64 *ops) {
   c64 y1 = ca * (o1[2] * x0 + o1[3] * x1) + cb * (o2[2] * x0 + o2[3] * x1);
   A[(size_t)(a * 2 + 0) * dr + c] = cvt<T>(y0);
   A[(size_t)(a * 2 + 1) * dr + c] = cvt<T>(y1);
+  }
 }
 
 // Bond-2 operator blocks over [l, r]:
@@ -397,13 +428,12 @@ __global__ void k_build(MpsDev m, int l, int r, const c64 *ops) {
   const int dl = b[j], dr = b[j + 1];
   const int Dl = (j == l) ? dl : 2 * dl;
   const int Dr = (j == r) ? dr : 2 * dr;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     int *w = wbd(m, s);
     w[j] = Dl;
     if (j == r) w[r + 1] = dr;
   }
-  if (e >= Dl * Dr) return;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < Dl * Dr; e += gridDim.x * blockDim.x) {
   const int a = e / Dr, c = e % Dr;
   const int ba = a >= dl, bc = c >= dr;   // branch of the row / column index
   cplx<T> *out = (j == l) ? scr<T>(m.T, m.T_cap, s) : wslot<T>(m, j, s);
@@ -430,20 +460,19 @@ __global__ void k_build(MpsDev m, int l, int r, const c64 *ops) {
   }
   out[(size_t)(a * 2 + 0) * Dr + c] = cvt<T>(y0);
   out[(size_t)(a * 2 + 1) * Dr + c] = cvt<T>(y1);
+  }
 }
 
 // QR in the left-to-right sweep: scratch T as (2 wb[j]) x wb[j+1] -> Q into
 // wslot j, R into scratch R; aux[0] = new bond p, aux[1] = old bond.
 template <typename T>
-__global__ void k_qr_lr(MpsDev m, int j) {
+__global__ void k_qr_lr(MpsDev m, int j, int lds_rows) {
   extern __shared__ char lds[];
   const int s = blockIdx.x;
   int *w = wbd(m, s);
   const int rows = 2 * w[j], cols = w[j + 1];
   const int p = rows < cols ? rows : cols;
-  c64 *vs = reinterpret_cast<c64 *>(lds);
-  double *vd = reinterpret_cast<double *>(vs + rows);
-  qr_block<T>(rows, cols, scr<T>(m.T, m.T_cap, s), wslot<T>(m, j, s), 0, scr<T>(m.R, m.R_cap, s), vs, vd);
+  qr_dispatch<T>(rows, cols, scr<T>(m.T, m.T_cap, s), wslot<T>(m, j, s), 0, scr<T>(m.R, m.R_cap, s), lds, lds_rows);
   if (threadIdx.x == 0) {
     auxp(m, s)[0] = p; auxp(m, s)[1] = cols;
     add_work(m, K_QR, qr_flops(rows, cols), (double)sizeof(cplx<T>) * ((double)rows * cols * 2 + (double)rows * p + (double)p * cols));
@@ -456,9 +485,8 @@ __global__ void k_absorb_lr(MpsDev m, int j) {
   const int s = blockIdx.z;
   int *w = wbd(m, s);
   const int p = auxp(m, s)[0], K = auxp(m, s)[1], N = 2 * w[j + 2];
-  if (blockIdx.y * GT < p && blockIdx.x * GT < N)
-    gemm_tile<T, T, T, T>(p, N, K, scr<T>(m.R, m.R_cap, s), K, 0, wslot<T>(m, j + 1, s), N, 0,
-                          scr<T>(m.T, m.T_cap, s), N, blockIdx.y, blockIdx.x);
+  gemm_all<T, T, T, T>(p, N, K, scr<T>(m.R, m.R_cap, s), K, 0, wslot<T>(m, j + 1, s), N, 0,
+                          scr<T>(m.T, m.T_cap, s), N);
   __syncthreads();
   if (first_block()) {
     w[j + 1] = p;
@@ -472,10 +500,8 @@ __global__ void k_gram(MpsDev m, int j) {
   const int s = blockIdx.z;
   int *w = wbd(m, s);
   const int L = w[j], nn = 2 * w[j + 1];
-  if (blockIdx.y * GT < nn && blockIdx.x * GT < nn)
-    gemm_tile<T, T, double, double>(nn, nn, L, scr<T>(m.T, m.T_cap, s), nn, 1,
-                                    scr<T>(m.T, m.T_cap, s), nn, 0, m.G + s * m.G_cap, nn,
-                                    blockIdx.y, blockIdx.x);
+  gemm_all<T, T, double, double>(nn, nn, L, scr<T>(m.T, m.T_cap, s), nn, 1,
+                                    scr<T>(m.T, m.T_cap, s), nn, 0, m.G + s * m.G_cap, nn);
   if (first_block())
     add_work(m, K_GRAM, gemm_flops(nn, nn, L), (double)sizeof(cplx<T>) * L * nn + 16.0 * nn * nn);
 }
@@ -485,14 +511,24 @@ __global__ void k_eig(MpsDev m, int j) {
   extern __shared__ char lds[];
   const int s = blockIdx.x;
   const int nn = 2 * wbd(m, s)[j + 1];
-  int *pos = reinterpret_cast<int *>(lds);
+  c64 *Gl = reinterpret_cast<c64 *>(lds);                 // used when nn <= kEigLdsN
+  c64 *Vl = Gl + kEigLdsN * kEigLdsN;
+  int *pos = reinterpret_cast<int *>(Vl + kEigLdsN * kEigLdsN);
   int *pp = pos + 1040, *pq = pp + 520;
   double *pc = reinterpret_cast<double *>(pq + 520);
   double *ps = pc + 520;
   c64 *pe = reinterpret_cast<c64 *>(ps + 520);
-  // eigenvectors are accumulated in V and written sorted back into G
+  c64 *Gg = m.G + s * m.G_cap;
+  c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
+  if (nn <= kEigLdsN) {       // small matrices: rotate in LDS, write the sorted vectors back
+    for (int e = threadIdx.x; e < nn * nn; e += TB) Gl[e] = Gg[e];
+    __syncthreads();
+    Gw = Gl;
+    Vw = Vl;
+  }
+  // eigenvectors are accumulated in V and written sorted into G (global)
   __shared__ int sweeps;
-  jacobi_block(nn, m.G + s * m.G_cap, m.V + s * m.V_cap, m.ev + s * m.ev_cap, m.G + s * m.G_cap,
+  jacobi_block(nn, Gw, Vw, m.ev + s * m.ev_cap, Gg,
                m.err, pos, pc, ps, pe, pp, pq, &sweeps,
                sizeof(T) == 8 ? 1e-18 : 1e-16, sizeof(T) == 8 ? 1e-15 : 1e-13);
   // algorithmic work: a Hermitian eigendecomposition with vectors, ~9 n^3 real
@@ -554,9 +590,8 @@ __global__ void k_ngemm(MpsDev m, int j) {
   const int s = blockIdx.z;
   int *w = wbd(m, s);
   const int L = w[j], nn = 2 * w[j + 1], k = auxp(m, s)[2];
-  if (blockIdx.y * GT < L && blockIdx.x * GT < k)
-    gemm_tile<T, T, T, T>(L, k, nn, scr<T>(m.T, m.T_cap, s), nn, 0, scr<T>(m.Vt, m.Vt_cap, s), k, 0,
-                          scr<T>(m.N, m.N_cap, s), k, blockIdx.y, blockIdx.x);
+  gemm_all<T, T, T, T>(L, k, nn, scr<T>(m.T, m.T_cap, s), nn, 0, scr<T>(m.Vt, m.Vt_cap, s), k, 0,
+                       scr<T>(m.N, m.N_cap, s), k);
   if (first_block())
     add_work(m, K_GEMM, gemm_flops(L, k, nn), (double)sizeof(cplx<T>) * ((double)L * nn + (double)nn * k + (double)L * k));
 }
@@ -567,9 +602,8 @@ __global__ void k_xgemm(MpsDev m, int j) {
   const int s = blockIdx.z;
   int *w = wbd(m, s);
   const int M = 2 * w[j - 1], L = auxp(m, s)[3], k = auxp(m, s)[2];
-  if (blockIdx.y * GT < M && blockIdx.x * GT < k)
-    gemm_tile<T, T, T, T>(M, k, L, wslot<T>(m, j - 1, s), L, 0, scr<T>(m.N, m.N_cap, s), k, 0,
-                          scr<T>(m.T, m.T_cap, s), k, blockIdx.y, blockIdx.x);
+  gemm_all<T, T, T, T>(M, k, L, wslot<T>(m, j - 1, s), L, 0, scr<T>(m.N, m.N_cap, s), k, 0,
+                          scr<T>(m.T, m.T_cap, s), k);
   __syncthreads();
   if (first_block()) {
     w[j] = k;
@@ -635,15 +669,15 @@ template <typename T>
 __global__ void k_copy_to_T(MpsDev m, int site, int conjt) {
   const int s = blockIdx.y;
   const int dl = bnd(m, s)[site], dr = bnd(m, s)[site + 1];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= dl * 2 * dr) return;
   const cplx<T> *A = slot<T>(m, site, s);
   cplx<T> *X = scr<T>(m.T, m.T_cap, s);
-  if (!conjt) {
-    X[e] = A[e];
-  } else {   // X = A^H with A viewed as dl x (2 dr)
-    int a = e / (2 * dr), c = e % (2 * dr);
-    X[(size_t)c * dl + a] = cj(A[e]);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < dl * 2 * dr; e += gridDim.x * blockDim.x) {
+    if (!conjt) {
+      X[e] = A[e];
+    } else {   // X = A^H with A viewed as dl x (2 dr)
+      int a = e / (2 * dr), c = e % (2 * dr);
+      X[(size_t)c * dl + a] = cj(A[e]);
+    }
   }
 }
 
@@ -651,21 +685,18 @@ template <typename T>
 __global__ void k_copy_from_T(MpsDev m, int site) {
   const int s = blockIdx.y;
   const int dl = bnd(m, s)[site], dr = bnd(m, s)[site + 1];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= dl * 2 * dr) return;
-  slot<T>(m, site, s)[e] = scr<T>(m.T, m.T_cap, s)[e];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < dl * 2 * dr; e += gridDim.x * blockDim.x)
+    slot<T>(m, site, s)[e] = scr<T>(m.T, m.T_cap, s)[e];
 }
 
 // Right move at c: T (2 bond[c] x bond[c+1]) = Q R; Q -> slot c.
 template <typename T>
-__global__ void k_qr_move_r(MpsDev m, int c) {
+__global__ void k_qr_move_r(MpsDev m, int c, int lds_rows) {
   extern __shared__ char lds[];
   const int s = blockIdx.x;
   const int rows = 2 * bnd(m, s)[c], cols = bnd(m, s)[c + 1];
   const int p = rows < cols ? rows : cols;
-  c64 *vs = reinterpret_cast<c64 *>(lds);
-  double *vd = reinterpret_cast<double *>(vs + rows);
-  qr_block<T>(rows, cols, scr<T>(m.T, m.T_cap, s), slot<T>(m, c, s), 0, scr<T>(m.R, m.R_cap, s), vs, vd);
+  qr_dispatch<T>(rows, cols, scr<T>(m.T, m.T_cap, s), slot<T>(m, c, s), 0, scr<T>(m.R, m.R_cap, s), lds, lds_rows);
   if (threadIdx.x == 0) {
     auxp(m, s)[0] = p; auxp(m, s)[1] = cols;
     add_work(m, K_QR, qr_flops(rows, cols), (double)sizeof(cplx<T>) * ((double)rows * cols * 2 + (double)rows * p + (double)p * cols));
@@ -674,14 +705,12 @@ __global__ void k_qr_move_r(MpsDev m, int c) {
 
 // Left move at c: T = A_c^H (2 bond[c+1] x bond[c]) = Q R; A_c <- Q^H.
 template <typename T>
-__global__ void k_qr_move_l(MpsDev m, int c) {
+__global__ void k_qr_move_l(MpsDev m, int c, int lds_rows) {
   extern __shared__ char lds[];
   const int s = blockIdx.x;
   const int rows = 2 * bnd(m, s)[c + 1], cols = bnd(m, s)[c];
   const int p = rows < cols ? rows : cols;
-  c64 *vs = reinterpret_cast<c64 *>(lds);
-  double *vd = reinterpret_cast<double *>(vs + rows);
-  qr_block<T>(rows, cols, scr<T>(m.T, m.T_cap, s), slot<T>(m, c, s), 1, scr<T>(m.R, m.R_cap, s), vs, vd);
+  qr_dispatch<T>(rows, cols, scr<T>(m.T, m.T_cap, s), slot<T>(m, c, s), 1, scr<T>(m.R, m.R_cap, s), lds, lds_rows);
   if (threadIdx.x == 0) {
     auxp(m, s)[0] = p; auxp(m, s)[1] = cols;
     add_work(m, K_QR, qr_flops(rows, cols), (double)sizeof(cplx<T>) * ((double)rows * cols * 2 + (double)rows * p + (double)p * cols));
@@ -693,9 +722,8 @@ template <typename T>
 __global__ void k_absorb_move_r(MpsDev m, int c) {
   const int s = blockIdx.z;
   const int p = auxp(m, s)[0], K = auxp(m, s)[1], N = 2 * bnd(m, s)[c + 2];
-  if (blockIdx.y * GT < p && blockIdx.x * GT < N)
-    gemm_tile<T, T, T, T>(p, N, K, scr<T>(m.R, m.R_cap, s), K, 0, slot<T>(m, c + 1, s), N, 0,
-                          scr<T>(m.T, m.T_cap, s), N, blockIdx.y, blockIdx.x);
+  gemm_all<T, T, T, T>(p, N, K, scr<T>(m.R, m.R_cap, s), K, 0, slot<T>(m, c + 1, s), N, 0,
+                          scr<T>(m.T, m.T_cap, s), N);
   if (first_block())
     add_work(m, K_GEMM, gemm_flops(p, N, K), (double)sizeof(cplx<T>) * ((double)p * K + (double)K * N + (double)p * N));
 }
@@ -705,9 +733,8 @@ template <typename T>
 __global__ void k_absorb_move_l(MpsDev m, int c) {
   const int s = blockIdx.z;
   const int p = auxp(m, s)[0], K = auxp(m, s)[1], M = 2 * bnd(m, s)[c - 1];
-  if (blockIdx.y * GT < M && blockIdx.x * GT < p)
-    gemm_tile<T, T, T, T>(M, p, K, slot<T>(m, c - 1, s), K, 0, scr<T>(m.R, m.R_cap, s), K, 1,
-                          scr<T>(m.T, m.T_cap, s), p, blockIdx.y, blockIdx.x);
+  gemm_all<T, T, T, T>(M, p, K, slot<T>(m, c - 1, s), K, 0, scr<T>(m.R, m.R_cap, s), K, 1,
+                          scr<T>(m.T, m.T_cap, s), p);
   if (first_block())
     add_work(m, K_GEMM, gemm_flops(M, p, K), (double)sizeof(cplx<T>) * ((double)M * K + (double)K * p + (double)M * p));
 }
@@ -734,9 +761,8 @@ __global__ void k_expect_f(MpsDev m, int j, const c64 *ops) {
   const int s = blockIdx.z;
   const int dl = bnd(m, s)[j], dr = bnd(m, s)[j + 1];
   const int N = 2 * dr;
-  if (blockIdx.y * GT < dl && blockIdx.x * GT < N)
-    gemm_tile<double, T, double, double>(dl, N, dl, m.E + s * m.E_cap, dl, 0, slot<T>(m, j, s), N, 0,
-                                         m.F + s * m.F_cap, N, blockIdx.y, blockIdx.x);
+  gemm_all<double, T, double, double>(dl, N, dl, m.E + s * m.E_cap, dl, 0, slot<T>(m, j, s), N, 0,
+                                         m.F + s * m.F_cap, N);
   if (first_block())
     add_work(m, K_EXPECT, gemm_flops(dl, N, dl), 16.0 * dl * dl + (double)sizeof(cplx<T>) * dl * N + 16.0 * dl * N);
 }
@@ -745,22 +771,21 @@ template <typename T>
 __global__ void k_expect_op(MpsDev m, int j, const c64 *o) {
   const int s = blockIdx.y;
   const int dl = bnd(m, s)[j], dr = bnd(m, s)[j + 1];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= dl * dr) return;
-  const int a = e / dr, c = e % dr;
   c64 *F = m.F + s * m.F_cap;
-  c64 f0 = F[(size_t)(a * 2 + 0) * dr + c], f1 = F[(size_t)(a * 2 + 1) * dr + c];
-  F[(size_t)(a * 2 + 0) * dr + c] = o[0] * f0 + o[1] * f1;
-  F[(size_t)(a * 2 + 1) * dr + c] = o[2] * f0 + o[3] * f1;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < dl * dr; e += gridDim.x * blockDim.x) {
+    const int a = e / dr, c = e % dr;
+    c64 f0 = F[(size_t)(a * 2 + 0) * dr + c], f1 = F[(size_t)(a * 2 + 1) * dr + c];
+    F[(size_t)(a * 2 + 0) * dr + c] = o[0] * f0 + o[1] * f1;
+    F[(size_t)(a * 2 + 1) * dr + c] = o[2] * f0 + o[3] * f1;
+  }
 }
 
 template <typename T>
 __global__ void k_expect_e(MpsDev m, int j) {
   const int s = blockIdx.z;
   const int dl = bnd(m, s)[j], dr = bnd(m, s)[j + 1];
-  if (blockIdx.y * GT < dr && blockIdx.x * GT < dr)
-    gemm_tile<T, double, double, double>(dr, dr, 2 * dl, slot<T>(m, j, s), dr, 1, m.F + s * m.F_cap, dr,
-                                         0, m.E + s * m.E_cap, dr, blockIdx.y, blockIdx.x);
+  gemm_all<T, double, double, double>(dr, dr, 2 * dl, slot<T>(m, j, s), dr, 1, m.F + s * m.F_cap, dr,
+                                         0, m.E + s * m.E_cap, dr);
   if (first_block())
     add_work(m, K_EXPECT, gemm_flops(dr, dr, 2 * dl), (double)sizeof(cplx<T>) * 2 * dl * dr + 16.0 * 2 * dl * dr + 16.0 * dr * dr);
 }
@@ -850,9 +875,18 @@ __global__ void k_outcome(MpsDev m, const uint64_t *snap_sign, int pivot, int dr
   if (threadIdx.x == 0) { negmask[blockIdx.x] = bn; mmask[blockIdx.x] = bm; }
 }
 
-inline dim3 gemm_grid(int maxM, int maxN, int S) {
-  return dim3((maxN + GT - 1) / GT, (maxM + GT - 1) / GT, S);
+// Blocks per shot: enough for about 8k blocks in flight over the batch, never
+// more than the largest tile count.
+inline int per_shot_blocks(long work_units, int S) {
+  long want = (8192 + S - 1) / S;
+  long b = work_units < want ? work_units : want;
+  return (int)(b < 1 ? 1 : b);
 }
+inline dim3 gemm_grid(int maxM, int maxN, int S) {
+  long tiles = (long)((maxM + GT - 1) / GT) * ((maxN + GT - 1) / GT);
+  return dim3(per_shot_blocks(tiles, S), 1, S);
+}
+inline int ew_blocks(long maxe, int S) { return per_shot_blocks((maxe + TB - 1) / TB, S); }
 inline int imin(int a, int b) { return a < b ? a : b; }
 // largest possible bond at bond index b (between sites b-1 and b)
 inline int dmax(const MpsDev &m, int b, int mult) {
@@ -871,7 +905,7 @@ template <typename T> void mps_init(const MpsDev &m, hipStream_t st) {
 
 template <typename T> void mps_apply_single(const MpsDev &m, int site, const c64 *d_ops, hipStream_t st) {
   int maxe = dmax(m, site, 1) * dmax(m, site + 1, 1);
-  KLAUNCH(K_BUILD, k_apply1<T>, dim3((maxe + TB - 1) / TB, m.S), dim3(TB), 0, st, m, site, d_ops);
+  KLAUNCH(K_BUILD, k_apply1<T>, dim3(ew_blocks(maxe, m.S), m.S), dim3(TB), 0, st, m, site, d_ops);
 }
 
 template <typename T> void mps_build(const MpsDev &m, int l, int r, const c64 *d_ops, hipStream_t st) {
@@ -880,16 +914,18 @@ template <typename T> void mps_build(const MpsDev &m, int l, int r, const c64 *d
     int a = (j == l ? 1 : 2) * dmax(m, j, 1), c = (j == r ? 1 : 2) * dmax(m, j + 1, 1);
     maxe = std::max(maxe, a * c);
   }
-  KLAUNCH(K_BUILD, k_build<T>, dim3((maxe + TB - 1) / TB, r - l + 1, m.S), dim3(TB), 0, st, m, l, r, d_ops);
+  KLAUNCH(K_BUILD, k_build<T>, dim3(ew_blocks(maxe, m.S), r - l + 1, m.S), dim3(TB), 0, st, m, l, r, d_ops);
 }
 
-static size_t qr_lds(int rows) { return (size_t)rows * sizeof(c64) + (size_t)rows * 2 * sizeof(double); }
+static size_t qr_lds(int rows) {
+  return (size_t)rows * sizeof(c64) + (size_t)rows * 2 * sizeof(double) + kQrLdsMat;
+}
 
 template <typename T> void mps_sweep_lr(const MpsDev &m, int l, int r, hipStream_t st) {
   for (int j = l; j < r; ++j) {
     int rows = 2 * (j == l ? dmax(m, j, 1) : 2 * dmax(m, j, 1));
     int cols = 2 * dmax(m, j + 1, 1);
-    KLAUNCH(K_QR, k_qr_lr<T>, dim3(m.S), dim3(TB), qr_lds(rows), st, m, j);
+    KLAUNCH(K_QR, k_qr_lr<T>, dim3(m.S), dim3(TB), qr_lds(rows), st, m, j, rows);
     int p = imin(rows, cols);
     int ncol = 2 * (j + 1 == r ? dmax(m, j + 2, 1) : 2 * dmax(m, j + 2, 1));
     KLAUNCH(K_GEMM, k_absorb_lr<T>, gemm_grid(p, ncol, m.S), dim3(TB), 0, st, m, j);
@@ -897,7 +933,8 @@ template <typename T> void mps_sweep_lr(const MpsDev &m, int l, int r, hipStream
 }
 
 static size_t eig_lds() {
-  return 1040 * sizeof(int) + 2 * 520 * sizeof(int) + 2 * 520 * sizeof(double) + 520 * sizeof(c64);
+  return 2 * kEigLdsN * kEigLdsN * sizeof(c64) + 1040 * sizeof(int) + 2 * 520 * sizeof(int) +
+         2 * 520 * sizeof(double) + 520 * sizeof(c64);
 }
 
 template <typename T> void mps_sweep_rl(const MpsDev &m, int l, int r, hipStream_t st) {
@@ -918,25 +955,25 @@ template <typename T> void mps_sweep_rl(const MpsDev &m, int l, int r, hipStream
 template <typename T> void mps_move_right(const MpsDev &m, int c, hipStream_t st) {
   int rows = 2 * dmax(m, c, 1), cols = dmax(m, c + 1, 1);
   int maxe = rows * cols;
-  KLAUNCH(K_BUILD, k_copy_to_T<T>, dim3((maxe + TB - 1) / TB, m.S), dim3(TB), 0, st, m, c, 0);
-  KLAUNCH(K_QR, k_qr_move_r<T>, dim3(m.S), dim3(TB), qr_lds(rows), st, m, c);
+  KLAUNCH(K_BUILD, k_copy_to_T<T>, dim3(ew_blocks(maxe, m.S), m.S), dim3(TB), 0, st, m, c, 0);
+  KLAUNCH(K_QR, k_qr_move_r<T>, dim3(m.S), dim3(TB), qr_lds(rows), st, m, c, rows);
   int p = imin(rows, cols), N = 2 * dmax(m, c + 2, 1);
   KLAUNCH(K_GEMM, k_absorb_move_r<T>, gemm_grid(p, N, m.S), dim3(TB), 0, st, m, c);
   KLAUNCH(K_BUILD, k_set_bond, dim3((m.S + 63) / 64), dim3(64), 0, st, m, c + 1);
   int maxe2 = p * N;
-  KLAUNCH(K_BUILD, k_copy_from_T<T>, dim3((maxe2 + TB - 1) / TB, m.S), dim3(TB), 0, st, m, c + 1);
+  KLAUNCH(K_BUILD, k_copy_from_T<T>, dim3(ew_blocks(maxe2, m.S), m.S), dim3(TB), 0, st, m, c + 1);
 }
 
 template <typename T> void mps_move_left(const MpsDev &m, int c, hipStream_t st) {
   int rows = 2 * dmax(m, c + 1, 1), cols = dmax(m, c, 1);
   int maxe = rows * cols;
-  KLAUNCH(K_BUILD, k_copy_to_T<T>, dim3((maxe + TB - 1) / TB, m.S), dim3(TB), 0, st, m, c, 1);
-  KLAUNCH(K_QR, k_qr_move_l<T>, dim3(m.S), dim3(TB), qr_lds(rows), st, m, c);
+  KLAUNCH(K_BUILD, k_copy_to_T<T>, dim3(ew_blocks(maxe, m.S), m.S), dim3(TB), 0, st, m, c, 1);
+  KLAUNCH(K_QR, k_qr_move_l<T>, dim3(m.S), dim3(TB), qr_lds(rows), st, m, c, rows);
   int p = imin(rows, cols), M = 2 * dmax(m, c - 1, 1);
   KLAUNCH(K_GEMM, k_absorb_move_l<T>, gemm_grid(M, p, m.S), dim3(TB), 0, st, m, c);
   KLAUNCH(K_BUILD, k_set_bond, dim3((m.S + 63) / 64), dim3(64), 0, st, m, c);
   int maxe2 = M * p;
-  KLAUNCH(K_BUILD, k_copy_from_T<T>, dim3((maxe2 + TB - 1) / TB, m.S), dim3(TB), 0, st, m, c - 1);
+  KLAUNCH(K_BUILD, k_copy_from_T<T>, dim3(ew_blocks(maxe2, m.S), m.S), dim3(TB), 0, st, m, c - 1);
 }
 
 template <typename T> void mps_normalize_site(const MpsDev &m, int site, hipStream_t st) {
@@ -950,7 +987,7 @@ template <typename T> void mps_expect(const MpsDev &m, int l, int r, const c64 *
   for (int j = l; j <= r; ++j) {
     int dl = dmax(m, j, 1), dr = dmax(m, j + 1, 1);
     KLAUNCH(K_EXPECT, k_expect_f<T>, gemm_grid(dl, 2 * dr, m.S), dim3(TB), 0, st, m, j, d_eops);
-    KLAUNCH(K_EXPECT, k_expect_op<T>, dim3((dl * dr + TB - 1) / TB, m.S), dim3(TB), 0, st, m, j,
+    KLAUNCH(K_EXPECT, k_expect_op<T>, dim3(ew_blocks((long)dl * dr, m.S), m.S), dim3(TB), 0, st, m, j,
                        d_eops + (size_t)(j - l) * 4);
     KLAUNCH(K_EXPECT, k_expect_e<T>, gemm_grid(dr, dr, m.S), dim3(TB), 0, st, m, j);
   }
@@ -981,7 +1018,21 @@ void launch_outcome(const MpsDev &m, const uint64_t *d_snap_sign, int pivot, int
                      d_u, d_forced, n_meas, mi, d_out, d_prob, d_negmask, d_mmask);
 }
 
+// Raise the dynamic-LDS limit of the kernels that stage matrices in LDS
+// (gfx950 has 160 KB per CU).  Returns the first HIP error, if any.
+template <typename T> hipError_t mps_prepare(int max_rows) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_eig<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)eig_lds());
+  const int q = (int)qr_lds(max_rows);
+  for (const void *f : {(const void *)k_qr_lr<T>, (const void *)k_qr_move_r<T>, (const void *)k_qr_move_l<T>}) {
+    hipError_t e2 = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, q);
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
+}
+
 #define INST(T)                                                                        \
+  template hipError_t mps_prepare<T>(int);                                            \
   template void mps_init<T>(const MpsDev &, hipStream_t);                             \
   template void mps_apply_single<T>(const MpsDev &, int, const c64 *, hipStream_t);   \
   template void mps_build<T>(const MpsDev &, int, int, const c64 *, hipStream_t);     \
