@@ -53,6 +53,7 @@ CLASS_BOUND = {
     "build": ("hbm", "hbm_GBs"),
     "select": ("hbm", "hbm_GBs"),
     "tableau": ("hbm", "hbm_GBs"),
+    "layer": ("alu", None),                 # fused layer kernel: mixed FP32 / FP64 work
 }
 
 
@@ -232,10 +233,16 @@ def main():
             achieved = d["flops"] / (d["ms"] / 1e3) / 1e12
             unit = "TFLOP/s"
         peak = PEAKS[peak_key]
+        if dom == "layer" and prec == "fp32" and d["flops"] > 0:
+            # FP64 Gram + eigen-solve at the FP64 peak, the rest at the FP32 peak
+            f64 = prof["layer_fp64_flops"]
+            f32 = d["flops"] - f64
+            peak = d["flops"] / (f32 / PEAKS["fp32_vector_TFs"] + f64 / PEAKS["fp64_vector_TFs"])
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": measured_traffic(dom), "kernel_class": dom,
                 "launches": d["launches"], "avg_launch_ms": per_launch_ms,
                 "algorithmic_flops_per_launch": d["flops"] / d["launches"],
+                "fp64_flops_share": (prof["layer_fp64_flops"] / d["flops"]) if dom == "layer" and d["flops"] else None,
                 "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
                 "share_of_step_time": d["ms"] / ms if ms > 0 else None}
     cpu = None

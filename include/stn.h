@@ -167,7 +167,8 @@ enum { STN_K_TABLEAU = 0,  /* tableau gates, rewrite, frame change */
        STN_K_EIGEN = 5,    /* FP64 Hermitian eigen-solve of the Gram */
        STN_K_SELECT = 6,   /* truncation selection, FP64 renormalisation */
        STN_K_EXPECT = 7,   /* measurement transfer matrices and outcomes */
-       STN_K_COUNT = 8 };
+       STN_K_LAYER = 8,    /* fused per-shot rotation-layer kernel (all of its work) */
+       STN_K_COUNT = 9 };
 
 /* Diagnostic profiling.  Bit k of class_mask times every later launch of
  * kernel class k with HIP events on the context stream and enables the
@@ -178,11 +179,19 @@ stn_status stn_profile(stn_ctx *ctx, unsigned class_mask);
 
 /* Reads (and clears the event list of) the profile: per class the summed
  * kernel milliseconds, algorithmic flops and bytes, and the number of timed
- * launches (arrays of STN_K_COUNT entries, any may be NULL), plus the total
- * number of Jacobi sweeps executed.  Synchronises. */
+ * launches (arrays of STN_K_COUNT entries, any may be NULL), the total number
+ * of Jacobi sweeps executed, and the FP64 part (Gram + eigen-solve) of the
+ * STN_K_LAYER flops.  Synchronises. */
 stn_status stn_profile_read(stn_ctx *ctx, double *host_ms, double *host_flops,
                             double *host_bytes, long long *host_launches,
-                            double *host_eig_sweeps);
+                            double *host_eig_sweeps, double *host_layer_fp64_flops);
+
+/* How stn_rotate schedules its kernels: 1 = one launch per kernel step for
+ * all shots (grids spread each product over many blocks; best for few
+ * shots), 2 = one launch per chunk of up to 64 rotations in which each block
+ * runs every step of one shot (best for many shots), 0 = automatic (2 when
+ * n_shots >= 64).  Results are identical up to rounding order. */
+stn_status stn_set_layer_mode(stn_ctx *ctx, int mode);
 
 /* Overwrite one MPS site tensor of one shot from the host (synchronises):
  * host_buf holds dl*2*dr complex elements in the layout of stn_get_site; the

@@ -146,6 +146,7 @@ struct stn_ctx {
   c64 *d_ops = nullptr, *d_eops = nullptr;
   int *d_err = nullptr;
   int center = 0;
+  int layer_mode = 0;              // 0 auto, 1 per-step kernels, 2 fused per-shot layer kernel
   std::vector<uint64_t> hx, hz;    // shadow of the shared bits
   uint8_t tables[9][16];           // per gate kind
   std::string err;
@@ -196,7 +197,7 @@ size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> 
   size_t o_tab = L.off(64);
   size_t o_ops = L.off((size_t)n * 8 * sizeof(c64)), o_eops = L.off((size_t)n * 4 * sizeof(c64));
   size_t o_err = L.off(4);
-  size_t o_work = L.off((size_t)(2 * K_COUNT + 1) * 8);
+  size_t o_work = L.off((size_t)(2 * K_COUNT + 2) * 8);
   // MPS slots
   std::vector<int64_t> site_off(n), site_cap(n), ws_off(n), ws_cap(n);
   int64_t so = 0, wo = 0, Tcap = 1;
@@ -414,6 +415,25 @@ stn_status rotate_impl(stn_ctx *c, const int32_t *qs, int n_rot, const double *t
       b.p[i] = p;
     }
     launch_tab_products(c->tab, b, c->d_pbits, c->d_psgn, c->d_err, c->st);
+    const bool fused = c->layer_mode == 2 || (c->layer_mode == 0 && c->S >= 64);
+    if (fused) {
+      RotLayer L{};
+      L.n_rot = cnt;
+      L.theta_base = r0;
+      L.center_in = c->center;
+      for (int i = 0; i < cnt; ++i) {
+        std::vector<uint64_t> px(c->W), pz(c->W);
+        shadow_product(c, b.p[i], px.data(), pz.data());
+        int l, r, piv;
+        span_of(c, px.data(), pz.data(), &l, &r, &piv);
+        if (l < 0) return fail(c, STN_EINVAL, "rotation Pauli is the identity");
+        L.l[i] = (int16_t)l;
+        L.r[i] = (int16_t)r;
+        if (l != r) c->center = l;     // the kernel leaves the centre at l after a multi-site step
+      }
+      mps_rot_layer<T>(c->mps, c->d_pbits, c->d_psgn, c->W, c->SW, theta, stride, L, c->st);
+      continue;
+    }
     for (int i = 0; i < cnt; ++i) {
       std::vector<uint64_t> px(c->W), pz(c->W);
       shadow_product(c, b.p[i], px.data(), pz.data());
@@ -610,13 +630,13 @@ stn_status stn_profile(stn_ctx *c, unsigned class_mask) {
   c->prof.used = 0;
   for (int k = 0; k < K_COUNT; ++k) { c->prof_ms[k] = 0; c->prof_launches[k] = 0; }
   c->mps.prof = class_mask ? 1 : 0;
-  hipError_t e = hipMemsetAsync(c->mps.work, 0, (size_t)(2 * K_COUNT + 1) * 8, c->st);
+  hipError_t e = hipMemsetAsync(c->mps.work, 0, (size_t)(2 * K_COUNT + 2) * 8, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
 }
 
 stn_status stn_profile_read(stn_ctx *c, double *ms, double *flops, double *bytes, long long *launches,
-                            double *eig_sweeps) {
+                            double *eig_sweeps, double *layer_fp64_flops) {
   if (!c) return STN_EINVAL;
   stn_status s = sync_status(c);
   if (s != STN_OK) return s;
@@ -627,7 +647,7 @@ stn_status stn_profile_read(stn_ctx *c, double *ms, double *flops, double *bytes
   }
   c->prof.recs.clear();
   c->prof.used = 0;
-  double w[2 * K_COUNT + 1];
+  double w[2 * K_COUNT + 2];
   hipError_t e = hipMemcpy(w, c->mps.work, sizeof(w), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
   for (int k = 0; k < K_COUNT; ++k) {
@@ -637,6 +657,7 @@ stn_status stn_profile_read(stn_ctx *c, double *ms, double *flops, double *bytes
     if (launches) launches[k] = c->prof_launches[k];
   }
   if (eig_sweeps) *eig_sweeps = w[2 * K_COUNT];
+  if (layer_fp64_flops) *layer_fp64_flops = w[2 * K_COUNT + 1];
   return STN_OK;
 }
 
@@ -719,6 +740,12 @@ stn_status stn_set_site(stn_ctx *c, int shot, int site, const void *buf, int dl,
   if (e == hipSuccess)
     e = hipMemcpy(c->mps.bond + (size_t)shot * (c->n + 1) + site, b, 8, hipMemcpyHostToDevice);
   return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
+}
+
+stn_status stn_set_layer_mode(stn_ctx *c, int mode) {
+  if (!c || mode < 0 || mode > 2) return STN_EINVAL;
+  c->layer_mode = mode;
+  return STN_OK;
 }
 
 stn_status stn_set_center(stn_ctx *c, int center) {

@@ -43,7 +43,7 @@ __host__ __device__ inline cplx<D> cvt(cplx<S> a) { return {(D)a.x, (D)a.y}; }
 
 // ------------------------------------------------------------- profiling
 // Launch classes for timing and algorithmic work accounting.
-enum { K_TABLEAU = 0, K_BUILD, K_QR, K_GEMM, K_GRAM, K_EIGEN, K_SELECT, K_EXPECT, K_COUNT };
+enum { K_TABLEAU = 0, K_BUILD, K_QR, K_GEMM, K_GRAM, K_EIGEN, K_SELECT, K_EXPECT, K_LAYER, K_COUNT };
 
 // Host-side recorder: when active, launches of the selected classes are
 // bracketed by HIP events on their stream.
@@ -132,7 +132,18 @@ struct MpsDev {
 // Site operator table of one two-term step: for site j in [l, r],
 // ops[(j - l) * 8 + {0..3}] = O1 (row-major 2x2), [+4..7] = O2.
 
+// One chunk of rotations of a layer for the fused per-shot kernel.
+struct RotLayer {
+  int n_rot;                    // rotations in this chunk (<= kProgBatch)
+  int theta_base;               // index of the chunk's first rotation in the angle array
+  int center_in;                // orthogonality centre on entry (same for every shot)
+  int16_t l[kProgBatch], r[kProgBatch];   // span of each rewritten Pauli
+};
+
 template <typename T> hipError_t mps_prepare(int max_rows);
+template <typename T>
+void mps_rot_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
+                   const double *d_theta, int64_t stride, const RotLayer &L, hipStream_t st);
 template <typename T> void mps_init(const MpsDev &m, hipStream_t st);
 template <typename T> void mps_apply_single(const MpsDev &m, int site, const c64 *d_ops, hipStream_t st);
 template <typename T> void mps_build(const MpsDev &m, int l, int r, const c64 *d_ops, hipStream_t st);

@@ -541,8 +541,7 @@ __global__ void k_eig(MpsDev m, int j) {
 // (at least 1); discarded weight w updates the fidelity; Vt = V[:, :k'] in T;
 // site j <- Vt^H as (k', 2, wb[j+1]); bond[j] = k', bond[j+1] = wb[j+1].
 template <typename T>
-__global__ void k_select(MpsDev m, int j) {
-  const int s = blockIdx.x;
+__device__ int select_body(const MpsDev &m, int s, int j) {
   int *w = wbd(m, s);
   const int nn = 2 * w[j + 1];
   const double *ev = m.ev + s * m.ev_cap;
@@ -582,7 +581,12 @@ __global__ void k_select(MpsDev m, int j) {
     bnd(m, s)[j] = k;
     bnd(m, s)[j + 1] = w[j + 1];
   }
+  __syncthreads();
+  return k;
 }
+
+template <typename T>
+__global__ void k_select(MpsDev m, int j) { select_body<T>(m, blockIdx.x, j); }
 
 // N = X (L x nn) * Vt (nn x k')
 template <typename T>
@@ -614,8 +618,7 @@ __global__ void k_xgemm(MpsDev m, int j) {
 // Centre at l: normalise scratch T (wb[l], 2, wb[l+1]) in FP64 and store it
 // in slot l; bond[l+1] = wb[l+1].
 template <typename T>
-__global__ void k_finish(MpsDev m, int l) {
-  const int s = blockIdx.x;
+__device__ void finish_body(const MpsDev &m, int s, int l) {
   int *w = wbd(m, s);
   const int cnt = w[l] * 2 * w[l + 1];
   const cplx<T> *X = scr<T>(m.T, m.T_cap, s);
@@ -633,7 +636,11 @@ __global__ void k_finish(MpsDev m, int l) {
     bnd(m, s)[l + 1] = w[l + 1];
     m.nrm[s] = n2;
   }
+  __syncthreads();
 }
+
+template <typename T>
+__global__ void k_finish(MpsDev m, int l) { finish_body<T>(m, blockIdx.x, l); }
 
 // In-place FP64 normalisation of one site (the centre).
 template <typename T>
@@ -875,6 +882,206 @@ __global__ void k_outcome(MpsDev m, const uint64_t *snap_sign, int pivot, int dr
   if (threadIdx.x == 0) { negmask[blockIdx.x] = bn; mmask[blockIdx.x] = bm; }
 }
 
+// ============================================================ fused layer
+// Shots are independent, so one block per shot can run a whole chunk of
+// rotations of a layer (centre moves, bond-2 blocks, QR sweep, Gram/eigen
+// truncation, renormalisation) with block barriers only: one launch per
+// chunk instead of ~10 launches per site, and every shot proceeds at its own
+// bond dimensions.  Same arithmetic as the per-step kernels.
+
+// All tiles of a product by the calling block.
+template <typename TA, typename TB_, typename TC, typename ACC>
+__device__ void blk_gemm(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
+                         const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc) {
+  const int ntm = (M + GT - 1) / GT, ntn = (N + GT - 1) / GT;
+  for (int t = 0; t < ntm * ntn; ++t)
+    gemm_tile<TA, TB_, TC, ACC>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, t / ntn, t % ntn);
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void blk_copy(cplx<T> *dst, const cplx<T> *src, int cnt) {
+  for (int e = threadIdx.x; e < cnt; e += TB) dst[e] = src[e];
+  __syncthreads();
+}
+
+// Centre move c -> c+1 (QR of A_c, R into A_{c+1}).
+template <typename T>
+__device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds, int lds_rows) {
+  int *b = bnd(m, s);
+  const int rows = 2 * b[c], cols = b[c + 1], N = 2 * b[c + 2];
+  const int p = rows < cols ? rows : cols;
+  cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
+  blk_copy<T>(X, slot<T>(m, c, s), rows * cols);
+  qr_dispatch<T>(rows, cols, X, slot<T>(m, c, s), 0, R, lds, lds_rows);
+  blk_gemm<T, T, T, T>(p, N, cols, R, cols, 0, slot<T>(m, c + 1, s), N, 0, X, N);
+  if (threadIdx.x == 0) {
+    b[c + 1] = p;
+    add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+    add_work(m, K_LAYER, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
+  }
+  __syncthreads();
+  blk_copy<T>(slot<T>(m, c + 1, s), X, p * N);
+}
+
+// Centre move c -> c-1 (LQ of A_c via the QR of A_c^H, L into A_{c-1}).
+template <typename T>
+__device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds, int lds_rows) {
+  int *b = bnd(m, s);
+  const int dl = b[c], dr = b[c + 1], M = 2 * b[c - 1];
+  const int rows = 2 * dr, cols = dl, p = rows < cols ? rows : cols;
+  cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
+  const cplx<T> *A = slot<T>(m, c, s);
+  for (int e = threadIdx.x; e < dl * 2 * dr; e += TB) {
+    int a = e / (2 * dr), cc = e % (2 * dr);
+    X[(size_t)cc * dl + a] = cj(A[e]);
+  }
+  __syncthreads();
+  qr_dispatch<T>(rows, cols, X, slot<T>(m, c, s), 1, R, lds, lds_rows);
+  blk_gemm<T, T, T, T>(M, p, cols, slot<T>(m, c - 1, s), cols, 0, R, cols, 1, X, p);
+  if (threadIdx.x == 0) {
+    b[c] = p;
+    add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+    add_work(m, K_LAYER, gemm_flops(M, p, cols), (double)sizeof(cplx<T>) * ((double)M * cols + (double)cols * p + (double)M * p));
+  }
+  __syncthreads();
+  blk_copy<T>(slot<T>(m, c - 1, s), X, M * p);
+}
+
+__device__ inline void rot_site_ops(const uint64_t *bx, const uint64_t *bz, int j, c64 *o2) {
+  site_op((int)((bx[j >> 6] >> (j & 63)) & 1ull), (int)((bz[j >> 6] >> (j & 63)) & 1ull), o2);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TB) k_rot_layer(MpsDev m, const uint64_t *pbits, const uint64_t *psgn,
+                                                  int W, int SW, const double *theta, int64_t stride,
+                                                  RotLayer L, int lds_rows) {
+  extern __shared__ char lds[];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  int *b = bnd(m, s), *w = wbd(m, s);
+  __shared__ c64 cf[2];
+  __shared__ int sweeps;
+  int c = L.center_in;
+  for (int i = 0; i < L.n_rot; ++i) {
+    const int l = L.l[i], r = L.r[i];
+    const uint64_t *bx = pbits + (size_t)i * 2 * W, *bz = bx + W;
+    if (tid == 0) {
+      const double th = theta[(int64_t)s * stride + L.theta_base + i];
+      if (!(th == th) || isinf(th)) atomicOr(m.err, STN_ERR_NUMERIC);
+      const double sg = ((psgn[(size_t)i * SW + (s >> 6)] >> (s & 63)) & 1ull) ? -1.0 : 1.0;
+      cf[0] = mk<double>(cos(th), 0);
+      cf[1] = mk<double>(0, -sg * sin(th));
+    }
+    __syncthreads();
+    const c64 ca = cf[0], cb = cf[1];
+    if (l == r) {                              // unitary on one site: no bond change
+      c64 o2[4];
+      rot_site_ops(bx, bz, l, o2);
+      const int dl = b[l], dr = b[l + 1];
+      cplx<T> *A = slot<T>(m, l, s);
+      for (int e = tid; e < dl * dr; e += TB) {
+        const int a = e / dr, cc = e % dr;
+        c64 x0 = cvt<double>(A[(size_t)(a * 2 + 0) * dr + cc]), x1 = cvt<double>(A[(size_t)(a * 2 + 1) * dr + cc]);
+        A[(size_t)(a * 2 + 0) * dr + cc] = cvt<T>(ca * x0 + cb * (o2[0] * x0 + o2[1] * x1));
+        A[(size_t)(a * 2 + 1) * dr + cc] = cvt<T>(ca * x1 + cb * (o2[2] * x0 + o2[3] * x1));
+      }
+      __syncthreads();
+      continue;
+    }
+    while (c < l) { blk_move_right<T>(m, s, c, lds, lds_rows); ++c; }
+    while (c > r) { blk_move_left<T>(m, s, c, lds, lds_rows); --c; }
+    // bond-2 blocks over [l, r]
+    for (int j = l; j <= r; ++j) {
+      const int dl = b[j], dr = b[j + 1];
+      const int Dl = (j == l) ? dl : 2 * dl, Dr = (j == r) ? dr : 2 * dr;
+      c64 o2[4];
+      rot_site_ops(bx, bz, j, o2);
+      cplx<T> *out = (j == l) ? scr<T>(m.T, m.T_cap, s) : wslot<T>(m, j, s);
+      const cplx<T> *A = slot<T>(m, j, s);
+      for (int e = tid; e < Dl * Dr; e += TB) {
+        const int a = e / Dr, cc = e % Dr;
+        const int ba = a >= dl, bc = cc >= dr;
+        int br = -1;
+        if (j == l) br = bc;
+        else if (j == r) br = ba;
+        else if (ba == bc) br = ba;
+        c64 y0 = mk<double>(0, 0), y1 = mk<double>(0, 0);
+        if (br >= 0) {
+          const int aa = (j == l) ? a : a - (ba ? dl : 0);
+          const int c2 = (j == r) ? cc : cc - (bc ? dr : 0);
+          c64 x0 = cvt<double>(A[(size_t)(aa * 2 + 0) * dr + c2]), x1 = cvt<double>(A[(size_t)(aa * 2 + 1) * dr + c2]);
+          if (br) { y0 = o2[0] * x0 + o2[1] * x1; y1 = o2[2] * x0 + o2[3] * x1; }
+          else { y0 = x0; y1 = x1; }
+          if (j == l) { const c64 k = br ? cb : ca; y0 = k * y0; y1 = k * y1; }
+        }
+        out[(size_t)(a * 2 + 0) * Dr + cc] = cvt<T>(y0);
+        out[(size_t)(a * 2 + 1) * Dr + cc] = cvt<T>(y1);
+      }
+      if (tid == 0) { w[j] = Dl; if (j == r) w[r + 1] = dr; }
+    }
+    __syncthreads();
+    // left-to-right QR sweep
+    for (int j = l; j < r; ++j) {
+      const int rows = 2 * w[j], cols = w[j + 1], N = 2 * w[j + 2];
+      const int p = rows < cols ? rows : cols;
+      cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
+      qr_dispatch<T>(rows, cols, X, wslot<T>(m, j, s), 0, R, lds, lds_rows);
+      blk_gemm<T, T, T, T>(p, N, cols, R, cols, 0, wslot<T>(m, j + 1, s), N, 0, X, N);
+      if (tid == 0) {
+        w[j + 1] = p;
+        add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+        add_work(m, K_LAYER, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
+      }
+      __syncthreads();
+    }
+    // right-to-left truncation sweep
+    for (int j = r; j > l; --j) {
+      const int Lx = w[j], nn = 2 * w[j + 1];
+      cplx<T> *X = scr<T>(m.T, m.T_cap, s);
+      c64 *Gg = m.G + s * m.G_cap;
+      blk_gemm<T, T, double, double>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn);
+      // eigen-solve (LDS when small); dynamic LDS is shared with the QR scratch
+      {
+        c64 *Gl = reinterpret_cast<c64 *>(lds);
+        c64 *Vl = Gl + kEigLdsN * kEigLdsN;
+        int *pos = reinterpret_cast<int *>(Vl + kEigLdsN * kEigLdsN);
+        int *pp = pos + 1040, *pq = pp + 520;
+        double *pc = reinterpret_cast<double *>(pq + 520);
+        double *ps = pc + 520;
+        c64 *pe = reinterpret_cast<c64 *>(ps + 520);
+        c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
+        if (nn <= kEigLdsN) {
+          for (int e = tid; e < nn * nn; e += TB) Gl[e] = Gg[e];
+          __syncthreads();
+          Gw = Gl;
+          Vw = Vl;
+        }
+        jacobi_block(nn, Gw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, &sweeps,
+                     sizeof(T) == 8 ? 1e-18 : 1e-16, sizeof(T) == 8 ? 1e-15 : 1e-13);
+        if (tid == 0) {
+          const double f64 = gemm_flops(nn, nn, Lx) + 36.0 * nn * nn * (double)nn;
+          add_work(m, K_LAYER, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
+          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
+          if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)sweeps);
+        }
+      }
+      const int k = select_body<T>(m, s, j);
+      cplx<T> *Nn = scr<T>(m.N, m.N_cap, s);
+      blk_gemm<T, T, T, T>(Lx, k, nn, X, nn, 0, scr<T>(m.Vt, m.Vt_cap, s), k, 0, Nn, k);
+      const int M = 2 * w[j - 1];
+      blk_gemm<T, T, T, T>(M, k, Lx, wslot<T>(m, j - 1, s), Lx, 0, Nn, k, 0, X, k);
+      if (tid == 0) {
+        w[j] = k;
+        add_work(m, K_LAYER, gemm_flops(Lx, k, nn) + gemm_flops(M, k, Lx),
+                 (double)sizeof(cplx<T>) * ((double)Lx * nn + (double)nn * k + 2.0 * Lx * k + (double)M * Lx + (double)M * k));
+      }
+      __syncthreads();
+    }
+    finish_body<T>(m, s, l);
+    c = l;
+  }
+}
+
 // Blocks per shot: enough for about 8k blocks in flight over the batch, never
 // more than the largest tile count.
 inline int per_shot_blocks(long work_units, int S) {
@@ -976,6 +1183,15 @@ template <typename T> void mps_move_left(const MpsDev &m, int c, hipStream_t st)
   KLAUNCH(K_BUILD, k_copy_from_T<T>, dim3(ew_blocks(maxe2, m.S), m.S), dim3(TB), 0, st, m, c - 1);
 }
 
+template <typename T>
+void mps_rot_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
+                   const double *d_theta, int64_t stride, const RotLayer &L, hipStream_t st) {
+  const int lds_rows = 4 * m.chi;
+  const size_t lds = std::max(qr_lds(lds_rows), eig_lds());
+  KLAUNCH(K_LAYER, k_rot_layer<T>, dim3(m.S), dim3(TB), lds, st, m, d_pbits, d_psgn, W, SW, d_theta,
+          stride, L, lds_rows);
+}
+
 template <typename T> void mps_normalize_site(const MpsDev &m, int site, hipStream_t st) {
   KLAUNCH(K_SELECT, k_normalize<T>, dim3(m.S), dim3(TB), 0, st, m, site);
 }
@@ -1024,6 +1240,11 @@ template <typename T> hipError_t mps_prepare(int max_rows) {
   hipError_t e = hipFuncSetAttribute((const void *)k_eig<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)eig_lds());
   const int q = (int)qr_lds(max_rows);
+  {
+    hipError_t e2 = hipFuncSetAttribute((const void *)k_rot_layer<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)std::max((size_t)q, eig_lds()));
+    if (e == hipSuccess) e = e2;
+  }
   for (const void *f : {(const void *)k_qr_lr<T>, (const void *)k_qr_move_r<T>, (const void *)k_qr_move_l<T>}) {
     hipError_t e2 = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, q);
     if (e == hipSuccess) e = e2;
@@ -1041,6 +1262,8 @@ template <typename T> hipError_t mps_prepare(int max_rows) {
   template void mps_move_right<T>(const MpsDev &, int, hipStream_t);                  \
   template void mps_move_left<T>(const MpsDev &, int, hipStream_t);                   \
   template void mps_normalize_site<T>(const MpsDev &, int, hipStream_t);              \
+  template void mps_rot_layer<T>(const MpsDev &, const uint64_t *, const uint64_t *, int, int,   \
+                                 const double *, int64_t, const RotLayer &, hipStream_t);       \
   template void mps_expect<T>(const MpsDev &, int, int, const c64 *, hipStream_t);
 INST(float)
 INST(double)

@@ -41,8 +41,8 @@ _lib = None
 EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn_clifford",
            "stn_rotate", "stn_measure", "stn_logprob", "stn_sync", "stn_get_tableau",
            "stn_get_bonds", "stn_get_site", "stn_center", "stn_profile", "stn_profile_read",
-           "stn_set_site", "stn_set_center"]
-K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect"]
+           "stn_set_site", "stn_set_center", "stn_set_layer_mode"]
+K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect", "layer"]
 
 
 def load(path: str = LIB_PATH):
@@ -88,7 +88,9 @@ def load(path: str = LIB_PATH):
     lib.stn_profile.restype = i32
     lib.stn_profile.argtypes = [vp, ctypes.c_uint]
     lib.stn_profile_read.restype = i32
-    lib.stn_profile_read.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.stn_profile_read.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.stn_set_layer_mode.restype = i32
+    lib.stn_set_layer_mode.argtypes = [vp, i32]
     _lib = lib
     return lib
 
@@ -117,7 +119,8 @@ class Simulator:
     """One libstn context on a CUDA (HIP) device with a torch-owned workspace."""
 
     def __init__(self, n_qubits: int, n_shots: int, chi_max: int, precision: str = "fp32",
-                 eps_cut: Optional[float] = None, device: str = "cuda:0", poison: bool = False):
+                 eps_cut: Optional[float] = None, device: str = "cuda:0", poison: bool = False,
+                 layer_mode: int = 0):
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -145,6 +148,8 @@ class Simulator:
             raise STNError(st, "stn_init failed")
         self.W = (n_qubits + 63) // 64
         self.SW = (n_shots + 63) // 64
+        if layer_mode:
+            self.set_layer_mode(layer_mode)
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -259,11 +264,17 @@ class Simulator:
         ms, fl, by = np.zeros(K), np.zeros(K), np.zeros(K)
         ln = np.zeros(K, np.int64)
         sw = np.zeros(1)
-        self._check(self.lib.stn_profile_read(self.ctx, *(a.ctypes.data_as(ctypes.c_void_p) for a in (ms, fl, by, ln, sw))))
+        f64 = np.zeros(1)
+        self._check(self.lib.stn_profile_read(self.ctx, *(a.ctypes.data_as(ctypes.c_void_p) for a in (ms, fl, by, ln, sw, f64))))
         out = {c: {"ms": float(ms[i]), "flops": float(fl[i]), "bytes": float(by[i]),
                    "launches": int(ln[i])} for i, c in enumerate(K_CLASSES)}
         out["eigen_sweeps"] = float(sw[0])
+        out["layer_fp64_flops"] = float(f64[0])
         return out
+
+    def set_layer_mode(self, mode: int):
+        """0 automatic, 1 per-step kernels, 2 fused per-shot layer kernel."""
+        self._check(self.lib.stn_set_layer_mode(self.ctx, int(mode)))
 
 
 # ----------------------------------------------------------------- circuits
@@ -317,12 +328,13 @@ def run_prepared(sim: Simulator, ops, start: int = 0, stop: Optional[int] = None
 
 
 def run_circuit(circ, chi_max: int, precision: str = "fp32", eps_cut: Optional[float] = None,
-                device: str = "cuda:0", forced: Optional[np.ndarray] = None, sim: Optional[Simulator] = None):
+                device: str = "cuda:0", forced: Optional[np.ndarray] = None, sim: Optional[Simulator] = None,
+                layer_mode: int = 0):
     """Simulates every shot of a workload Circuit on the GPU.  Returns a dict
     with records [S, M] uint8, prob [S, M], logp [S], trunc_err [S] (numpy)
     and the Simulator (for tableau / MPS inspection)."""
     if sim is None:
-        sim = Simulator(circ.n, circ.n_shots, chi_max, precision, eps_cut, device)
+        sim = Simulator(circ.n, circ.n_shots, chi_max, precision, eps_cut, device, layer_mode=layer_mode)
     ops = prepare(circ, device, forced)
     res = run_prepared(sim, ops)
     lp, te = sim.logprob()

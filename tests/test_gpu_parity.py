@@ -61,10 +61,10 @@ def mps_fidelity(sim, shot, omps):
     return 1 - ov
 
 
-def run_parity(B, circ, chi, prec, shots, *, check_mps=True, tie=None):
-    say(f"parity n={circ.n} S={circ.n_shots} chi={chi} {prec}")
+def run_parity(B, circ, chi, prec, shots, *, check_mps=True, tie=None, mode=0):
+    say(f"parity n={circ.n} S={circ.n_shots} chi={chi} {prec} layer mode {mode}")
     eps = EPS[prec]
-    g = B.run_circuit(circ, chi, prec, eps)
+    g = B.run_circuit(circ, chi, prec, eps, layer_mode=mode)
     ores = {s: ostn.run_shot(circ, s, chi_max=chi, eps_cut=eps) for s in shots}
     tie = tie if tie is not None else (1e-9 if prec == "fp64" else 1e-4)
     cond = [s for s in shots if ores[s].cut_sensitivity <= MAX_SENS[prec]]
@@ -83,7 +83,7 @@ def run_parity(B, circ, chi, prec, shots, *, check_mps=True, tie=None):
     # probabilities with the oracle's records forced on the GPU side
     forced = np.array([ores[s].record if s in ores else g["records"][s]
                        for s in range(circ.n_shots)], np.uint8)
-    gf = B.run_circuit(circ, chi, prec, eps, forced=forced)
+    gf = B.run_circuit(circ, chi, prec, eps, forced=forced, layer_mode=mode)
     worst = 0.0
     for s in shots:
         po = np.array(ores[s].prob)
@@ -136,20 +136,22 @@ def test_random_gate_set_tableau(B):
     run_parity(B, circ, 64, "fp64", range(5))
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_d3_crosstalk_no_truncation(B, prec):
+def test_d3_crosstalk_no_truncation(B, prec, mode):
     circ = W.memory_circuit(3, 3, 8, seed=11, theta_nn=0.05, p=0.0)
-    run_parity(B, circ, 64, prec, range(8))
+    run_parity(B, circ, 64, prec, range(8), mode=mode)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_d3_noise_nnn_hard_truncation(B, prec):
+def test_d3_noise_nnn_hard_truncation(B, prec, mode):
     """chi_max = 4 binds hard (a few % of the weight discarded per shot): the
     trajectory must follow the oracle's.  Shot 4 of this circuit drives a
     Householder QR whose pivot entry is ~1e-23 (regression case for norms
     and phases formed in float)."""
     circ = W.memory_circuit(3, 2, 6, seed=23, theta_law="per_coupling", nnn=True, p=0.01)
-    run_parity(B, circ, 4, prec, range(6))
+    run_parity(B, circ, 4, prec, range(6), mode=mode)
 
 
 @pytest.mark.parametrize("prec,chi", [("fp64", 8), ("fp32", 8), ("fp32", 12)])
@@ -159,14 +161,29 @@ def test_d3_noise_nnn_truncating(B, prec, chi):
     run_parity(B, circ, chi, prec, range(6))
 
 
-def test_d5_first_round_fp32(B):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_d5_first_round_fp32(B, mode):
     circ = W.memory_circuit(5, 1, 8, seed=21, theta_law="per_coupling", nnn=True, p=1e-3)
-    run_parity(B, circ, 256, "fp32", range(4))
+    run_parity(B, circ, 256, "fp32", range(4), mode=mode)
 
 
-def test_per_shot_theta(B):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_per_shot_theta(B, mode):
     circ = W.memory_circuit(3, 2, 6, seed=31, theta_law="per_shot", theta_range=(0.01, 0.08), nnn=True)
-    run_parity(B, circ, 16, "fp64", range(6))
+    run_parity(B, circ, 16, "fp64", range(6), mode=mode)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_layer_modes_agree(B, prec):
+    """The fused per-shot layer kernel and the per-step kernels give the same
+    records and probabilities (up to rounding order) on 96 shots."""
+    circ = W.memory_circuit(3, 2, 96, seed=43, theta_law="per_coupling", nnn=True, p=0.01)
+    a = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=1)
+    b = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=2)
+    same = np.all(a["records"] == b["records"], axis=1)
+    assert same.mean() > 0.95
+    rel = np.abs(a["prob"][same] - b["prob"][same]) / a["prob"][same]
+    assert rel.max() <= (1e-10 if prec == "fp64" else 1e-5)
 
 
 def test_forced_zero_probability_is_reported(B):
@@ -202,10 +219,11 @@ def test_bad_arguments(B):
     sim.sync()
 
 
-def test_repeat_is_bit_identical(B):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_repeat_is_bit_identical(B, mode):
     circ = W.memory_circuit(3, 2, 16, seed=41, theta_nn=0.06, p=0.01)
-    a = B.run_circuit(circ, 8, "fp32")
-    b = B.run_circuit(circ, 8, "fp32")
+    a = B.run_circuit(circ, 8, "fp32", layer_mode=mode)
+    b = B.run_circuit(circ, 8, "fp32", layer_mode=mode)
     assert np.array_equal(a["records"], b["records"])
     assert np.array_equal(a["prob"], b["prob"])
     assert np.array_equal(a["sim"].bonds(), b["sim"].bonds())
