@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-all", action="store_true")
+    ap.add_argument("--layer-mode", type=int, default=0, help="0 automatic, 1 per-step kernels, 2 fused")
+    ap.add_argument("--layer-threads", type=int, default=0, help="threads per shot of the fused kernel")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -183,7 +185,8 @@ def main():
     eps = stn.DEFAULT_EPS[stn.STN_FP64 if prec == "fp64" else stn.STN_FP32]
     dev = "cuda:0"
     print(f"# building inputs: {args.config} shots={circ.n_shots}", file=sys.stderr, flush=True)
-    sim = stn.Simulator(circ.n, circ.n_shots, chi, prec, eps, dev)
+    sim = stn.Simulator(circ.n, circ.n_shots, chi, prec, eps, dev, layer_mode=args.layer_mode,
+                        layer_threads=args.layer_threads)
     ops = stn.prepare(circ, dev)
     rounds = split_rounds(ops)
     W, K = args.warmup, args.steps
@@ -198,7 +201,7 @@ def main():
         print(f"# warmup round {r + 1}: {time.perf_counter() - t:.2f} s, max bond "
               f"{int(sim.bonds().max())}", file=sys.stderr, flush=True)
     # dominant-class timing: all classes when asked, else the expected heaviest
-    sim.profile(None if args.profile_all else ["eigen", "qr", "gemm", "gram"])
+    sim.profile(None if args.profile_all else ["eigen", "qr", "gemm", "gram", "layer"])
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()

@@ -193,6 +193,11 @@ stn_status stn_profile_read(stn_ctx *ctx, double *host_ms, double *host_flops,
  * n_shots >= 64).  Results are identical up to rounding order. */
 stn_status stn_set_layer_mode(stn_ctx *ctx, int mode);
 
+/* Threads per shot of the fused layer kernel: 64 (one wavefront per shot),
+ * 128 (the default) or 256.  A tuning knob: results agree to rounding order.
+ * STN_EINVAL for any other value. */
+stn_status stn_set_layer_threads(stn_ctx *ctx, int threads);
+
 /* Overwrite one MPS site tensor of one shot from the host (synchronises):
  * host_buf holds dl*2*dr complex elements in the layout of stn_get_site; the
  * shot's bonds site and site+1 become dl and dr.  The caller keeps the

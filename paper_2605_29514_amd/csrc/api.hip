@@ -147,6 +147,7 @@ struct stn_ctx {
   int *d_err = nullptr;
   int center = 0;
   int layer_mode = 0;              // 0 auto, 1 per-step kernels, 2 fused per-shot layer kernel
+  int layer_threads = 128;         // threads per shot of the fused kernel
   std::vector<uint64_t> hx, hz;    // shadow of the shared bits
   uint8_t tables[9][16];           // per gate kind
   std::string err;
@@ -227,6 +228,8 @@ size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> 
   size_t o_ev = L.off((size_t)nn * S * 8);
   size_t o_E = L.off((size_t)chi_eff * chi_eff * S * sizeof(c64)),
          o_F = L.off((size_t)chi_eff * 2 * chi_eff * S * sizeof(c64));
+  const int64_t Jcap = (int64_t)align_up(layer_fallback_bytes((int)chi_eff));
+  size_t o_J = L.off((size_t)Jcap * S);
   if (ctx && base) {
     ctx->n = n; ctx->S = S; ctx->chi = chi; ctx->prec = c.precision; ctx->W = W; ctx->SW = SW;
     ctx->esz = esz;
@@ -255,6 +258,7 @@ size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> 
     m.ev = (double *)(base + o_ev); m.ev_cap = nn;
     m.E = (c64 *)(base + o_E); m.E_cap = chi_eff * chi_eff;
     m.F = (c64 *)(base + o_F); m.F_cap = chi_eff * 2 * chi_eff;
+    m.J = base + o_J; m.J_cap = Jcap;
     m.logp = (double *)(base + o_logp); m.fid = (double *)(base + o_fid);
     m.p0 = (double *)(base + o_p0); m.nrm = (double *)(base + o_nrm);
     m.coef = (c64 *)(base + o_coef);
@@ -431,7 +435,7 @@ stn_status rotate_impl(stn_ctx *c, const int32_t *qs, int n_rot, const double *t
         L.r[i] = (int16_t)r;
         if (l != r) c->center = l;     // the kernel leaves the centre at l after a multi-site step
       }
-      mps_rot_layer<T>(c->mps, c->d_pbits, c->d_psgn, c->W, c->SW, theta, stride, L, c->st);
+      mps_rot_layer<T>(c->mps, c->d_pbits, c->d_psgn, c->W, c->SW, theta, stride, L, c->layer_threads, c->st);
       continue;
     }
     for (int i = 0; i < cnt; ++i) {
@@ -528,6 +532,7 @@ stn_status stn_init(stn_ctx **out, const stn_config *cfg, void *ws, size_t bytes
   {
     int max_rows = 4 * c->chi;                           // QR rows of a doubled tensor
     hipError_t pe = c->prec == STN_FP64 ? mps_prepare<double>(max_rows) : mps_prepare<float>(max_rows);
+    if (pe == hipSuccess) pe = c->prec == STN_FP64 ? layer_prepare<double>() : layer_prepare<float>();
     if (pe != hipSuccess) {
       delete c;
       return STN_EDEVICE;
@@ -745,6 +750,12 @@ stn_status stn_set_site(stn_ctx *c, int shot, int site, const void *buf, int dl,
 stn_status stn_set_layer_mode(stn_ctx *c, int mode) {
   if (!c || mode < 0 || mode > 2) return STN_EINVAL;
   c->layer_mode = mode;
+  return STN_OK;
+}
+
+stn_status stn_set_layer_threads(stn_ctx *c, int threads) {
+  if (!c || (threads != 64 && threads != 128 && threads != 256)) return STN_EINVAL;
+  c->layer_threads = threads;
   return STN_OK;
 }
 

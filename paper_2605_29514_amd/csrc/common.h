@@ -121,6 +121,7 @@ struct MpsDev {
   double *ev; int64_t ev_cap;   // eigenvalues
   c64 *E;    int64_t E_cap;     // transfer matrix (FP64)
   c64 *F;    int64_t F_cap;
+  void *J;   int64_t J_cap;     // bytes: fused-kernel fallbacks (reflectors, Jacobi pairs)
   double *logp, *fid, *p0, *nrm;  // [S]
   c64 *coef;                    // [S][2]  (a, b)
   int *err;
@@ -141,9 +142,12 @@ struct RotLayer {
 };
 
 template <typename T> hipError_t mps_prepare(int max_rows);
+template <typename T> hipError_t layer_prepare();
+size_t layer_fallback_bytes(int chi);
+// nt: threads per shot (64, 128 or 256)
 template <typename T>
 void mps_rot_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
-                   const double *d_theta, int64_t stride, const RotLayer &L, hipStream_t st);
+                   const double *d_theta, int64_t stride, const RotLayer &L, int nt, hipStream_t st);
 template <typename T> void mps_init(const MpsDev &m, hipStream_t st);
 template <typename T> void mps_apply_single(const MpsDev &m, int site, const c64 *d_ops, hipStream_t st);
 template <typename T> void mps_build(const MpsDev &m, int l, int r, const c64 *d_ops, hipStream_t st);

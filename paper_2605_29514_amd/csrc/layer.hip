@@ -1,0 +1,313 @@
+// Fused per-shot rotation-layer kernel of the STN step (Sec. IV.A-B).
+//
+// Shots are independent, so one block per shot runs a whole chunk of
+// rotations (centre moves, bond-2 operator blocks, left-to-right QR sweep,
+// right-to-left FP64 Gram/eigen truncation, FP64 renormalisation) with block
+// barriers only: one launch per chunk instead of ~10 launches per site, and
+// every shot proceeds at its own bond dimensions.  The block size NT (64, 128
+// or 256 threads per shot) is a launch parameter: with 64 threads a shot is
+// one wavefront and a barrier costs almost nothing, so 1024 shots fill the
+// 1024 SIMDs of the chip; larger blocks give a single shot more lanes when
+// there are few shots or large bonds.
+//
+// Small operands live in one dynamic LDS region that the phases overlay
+// (QR matrix, GEMM staging, Jacobi matrices); operands beyond its size stay
+// in the shot's global scratch, so every bond up to chi_max is handled.
+#include "linalg.h"
+
+#include <algorithm>
+
+namespace {
+
+using namespace stnk;
+
+constexpr int kLdsEigN = 32;              // Jacobi G and V in LDS up to this order
+constexpr int kLdsQrRows = 64;            // reflector vectors in LDS up to this many rows
+constexpr size_t kLdsQrMat = 16 * 1024;   // QR operand in LDS up to this many bytes
+constexpr int kLdsPairs = 64;             // Jacobi pair tables in LDS up to this order
+
+// Dynamic LDS layout (bytes).  U: union of the phase operands.
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t kU = cmax(cmax(2 * kLdsEigN * kLdsEigN * sizeof(c64), kLdsQrMat), GemmStage<double>::bytes);
+constexpr size_t kVs = kU;                                    // c64[kLdsQrRows]
+constexpr size_t kVd = kVs + kLdsQrRows * sizeof(c64);       // double[2 kLdsQrRows]
+constexpr size_t kPe = kVd + 2 * kLdsQrRows * sizeof(double);  // c64[kLdsPairs/2 + 1]
+constexpr size_t kPc = kPe + (kLdsPairs / 2 + 1) * sizeof(c64);
+constexpr size_t kPs = kPc + (kLdsPairs / 2 + 1) * sizeof(double);
+constexpr size_t kPos = kPs + (kLdsPairs / 2 + 1) * sizeof(double);
+constexpr size_t kPp = kPos + (kLdsPairs + 2) * sizeof(int);
+constexpr size_t kPq = kPp + (kLdsPairs / 2 + 1) * sizeof(int);
+constexpr size_t kWp = (kPq + (kLdsPairs / 2 + 1) * sizeof(int) + 15) / 16 * 16;
+constexpr size_t lds_bytes(int nt) { return kWp + nt * sizeof(c64); }
+
+// Global fallbacks in the shot's J scratch (bytes): reflector vectors for
+// up to 4 chi rows, then the pair tables for orders up to 2 chi.
+struct Fallback {
+  c64 *vs; double *vd;
+  c64 *pe; double *pc, *ps; int *pos, *pp, *pq;
+};
+__device__ inline Fallback fallback(const MpsDev &m, int s) {
+  char *b = reinterpret_cast<char *>(m.J) + (size_t)s * m.J_cap;
+  const int rows = 4 * m.chi + 2, P = 2 * m.chi + 2;
+  Fallback f;
+  f.vs = reinterpret_cast<c64 *>(b);
+  f.pe = f.vs + rows;
+  f.vd = reinterpret_cast<double *>(f.pe + P / 2 + 1);
+  f.pc = f.vd + 2 * rows;
+  f.ps = f.pc + P / 2 + 1;
+  f.pos = reinterpret_cast<int *>(f.ps + P / 2 + 1);
+  f.pp = f.pos + P + 2;
+  f.pq = f.pp + P / 2 + 1;
+  return f;
+}
+
+template <typename TA, typename TB_, typename TC, typename ACC, int NT>
+__device__ void blk_gemm(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
+                         const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, char *lds) {
+  gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds);
+  __syncthreads();
+}
+
+template <typename T, int NT>
+__device__ void blk_copy(cplx<T> *dst, const cplx<T> *src, int cnt) {
+  for (int e = threadIdx.x; e < cnt; e += NT) dst[e] = src[e];
+  __syncthreads();
+}
+
+// QR of the rows x cols matrix at A (global, may be overwritten): staged in
+// LDS when it fits.  Q -> Qd (qt as in qr_block), R -> Rd.
+template <typename T, int NT>
+__device__ void blk_qr(const MpsDev &m, int s, int rows, int cols, cplx<T> *A, cplx<T> *Qd, int qt,
+                       cplx<T> *Rd, char *lds) {
+  const Fallback f = fallback(m, s);
+  c64 *vs = rows <= kLdsQrRows ? reinterpret_cast<c64 *>(lds + kVs) : f.vs;
+  double *vd = rows <= kLdsQrRows ? reinterpret_cast<double *>(lds + kVd) : f.vd;
+  c64 *wp = reinterpret_cast<c64 *>(lds + kWp);
+  if ((size_t)rows * cols * sizeof(cplx<T>) <= kLdsQrMat) {
+    cplx<T> *Al = reinterpret_cast<cplx<T> *>(lds);
+    blk_copy<T, NT>(Al, A, rows * cols);
+    qr_block<T, NT>(rows, cols, Al, Qd, qt, Rd, vs, vd, wp);
+  } else {
+    qr_block<T, NT>(rows, cols, A, Qd, qt, Rd, vs, vd, wp);
+  }
+}
+
+// Centre move c -> c+1 (QR of A_c, R into A_{c+1}).
+template <typename T, int NT>
+__device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds) {
+  int *b = bnd(m, s);
+  const int rows = 2 * b[c], cols = b[c + 1], N = 2 * b[c + 2];
+  const int p = rows < cols ? rows : cols;
+  cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
+  blk_copy<T, NT>(X, slot<T>(m, c, s), rows * cols);
+  blk_qr<T, NT>(m, s, rows, cols, X, slot<T>(m, c, s), 0, R, lds);
+  blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, slot<T>(m, c + 1, s), N, 0, X, N, lds);
+  if (threadIdx.x == 0) {
+    b[c + 1] = p;
+    add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+    add_work(m, K_LAYER, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
+  }
+  __syncthreads();
+  blk_copy<T, NT>(slot<T>(m, c + 1, s), X, p * N);
+}
+
+// Centre move c -> c-1 (LQ of A_c via the QR of A_c^H, L into A_{c-1}).
+template <typename T, int NT>
+__device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds) {
+  int *b = bnd(m, s);
+  const int dl = b[c], dr = b[c + 1], M = 2 * b[c - 1];
+  const int rows = 2 * dr, cols = dl, p = rows < cols ? rows : cols;
+  cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
+  const cplx<T> *A = slot<T>(m, c, s);
+  for (int e = threadIdx.x; e < dl * 2 * dr; e += NT) {
+    int a = e / (2 * dr), cc = e % (2 * dr);
+    X[(size_t)cc * dl + a] = cj(A[e]);
+  }
+  __syncthreads();
+  blk_qr<T, NT>(m, s, rows, cols, X, slot<T>(m, c, s), 1, R, lds);
+  blk_gemm<T, T, T, T, NT>(M, p, cols, slot<T>(m, c - 1, s), cols, 0, R, cols, 1, X, p, lds);
+  if (threadIdx.x == 0) {
+    b[c] = p;
+    add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+    add_work(m, K_LAYER, gemm_flops(M, p, cols), (double)sizeof(cplx<T>) * ((double)M * cols + (double)cols * p + (double)M * p));
+  }
+  __syncthreads();
+  blk_copy<T, NT>(slot<T>(m, c - 1, s), X, M * p);
+}
+
+__device__ inline void rot_site_ops(const uint64_t *bx, const uint64_t *bz, int j, c64 *o2) {
+  site_op(bitw(bx, j), bitw(bz, j), o2);
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, const uint64_t *psgn,
+                                              int W, int SW, const double *theta, int64_t stride,
+                                              RotLayer L) {
+  extern __shared__ __align__(16) char lds[];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  int *b = bnd(m, s), *w = wbd(m, s);
+  __shared__ c64 cf[2];
+  __shared__ int sweeps;
+  int c = L.center_in;
+  for (int i = 0; i < L.n_rot; ++i) {
+    const int l = L.l[i], r = L.r[i];
+    const uint64_t *bx = pbits + (size_t)i * 2 * W, *bz = bx + W;
+    if (tid == 0) {
+      const double th = theta[(int64_t)s * stride + L.theta_base + i];
+      if (!(th == th) || isinf(th)) atomicOr(m.err, STN_ERR_NUMERIC);
+      const double sg = ((psgn[(size_t)i * SW + (s >> 6)] >> (s & 63)) & 1ull) ? -1.0 : 1.0;
+      cf[0] = mk<double>(cos(th), 0);
+      cf[1] = mk<double>(0, -sg * sin(th));
+    }
+    __syncthreads();
+    const c64 ca = cf[0], cb = cf[1];
+    if (l == r) {                              // unitary on one site: no bond change
+      c64 o2[4];
+      rot_site_ops(bx, bz, l, o2);
+      const int dl = b[l], dr = b[l + 1];
+      cplx<T> *A = slot<T>(m, l, s);
+      for (int e = tid; e < dl * dr; e += NT) {
+        const int a = e / dr, cc = e % dr;
+        c64 x0 = cvt<double>(A[(size_t)(a * 2 + 0) * dr + cc]), x1 = cvt<double>(A[(size_t)(a * 2 + 1) * dr + cc]);
+        A[(size_t)(a * 2 + 0) * dr + cc] = cvt<T>(ca * x0 + cb * (o2[0] * x0 + o2[1] * x1));
+        A[(size_t)(a * 2 + 1) * dr + cc] = cvt<T>(ca * x1 + cb * (o2[2] * x0 + o2[3] * x1));
+      }
+      __syncthreads();
+      continue;
+    }
+    while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
+    while (c > r) { blk_move_left<T, NT>(m, s, c, lds); --c; }
+    // bond-2 blocks over [l, r]
+    for (int j = l; j <= r; ++j) {
+      const int dl = b[j], dr = b[j + 1];
+      const int Dl = (j == l) ? dl : 2 * dl, Dr = (j == r) ? dr : 2 * dr;
+      c64 o2[4];
+      rot_site_ops(bx, bz, j, o2);
+      cplx<T> *out = (j == l) ? scr<T>(m.T, m.T_cap, s) : wslot<T>(m, j, s);
+      const cplx<T> *A = slot<T>(m, j, s);
+      for (int e = tid; e < Dl * Dr; e += NT) {
+        const int a = e / Dr, cc = e % Dr;
+        const int ba = a >= dl, bc = cc >= dr;
+        int br = -1;
+        if (j == l) br = bc;
+        else if (j == r) br = ba;
+        else if (ba == bc) br = ba;
+        c64 y0 = mk<double>(0, 0), y1 = mk<double>(0, 0);
+        if (br >= 0) {
+          const int aa = (j == l) ? a : a - (ba ? dl : 0);
+          const int c2 = (j == r) ? cc : cc - (bc ? dr : 0);
+          c64 x0 = cvt<double>(A[(size_t)(aa * 2 + 0) * dr + c2]), x1 = cvt<double>(A[(size_t)(aa * 2 + 1) * dr + c2]);
+          if (br) { y0 = o2[0] * x0 + o2[1] * x1; y1 = o2[2] * x0 + o2[3] * x1; }
+          else { y0 = x0; y1 = x1; }
+          if (j == l) { const c64 k = br ? cb : ca; y0 = k * y0; y1 = k * y1; }
+        }
+        out[(size_t)(a * 2 + 0) * Dr + cc] = cvt<T>(y0);
+        out[(size_t)(a * 2 + 1) * Dr + cc] = cvt<T>(y1);
+      }
+      if (tid == 0) { w[j] = Dl; if (j == r) w[r + 1] = dr; }
+    }
+    __syncthreads();
+    // left-to-right QR sweep: B_j = Q R, Q -> workspace slot j, R B_{j+1} -> T
+    for (int j = l; j < r; ++j) {
+      const int rows = 2 * w[j], cols = w[j + 1], N = 2 * w[j + 2];
+      const int p = rows < cols ? rows : cols;
+      cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
+      blk_qr<T, NT>(m, s, rows, cols, X, wslot<T>(m, j, s), 0, R, lds);
+      blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, wslot<T>(m, j + 1, s), N, 0, X, N, lds);
+      if (tid == 0) {
+        w[j + 1] = p;
+        add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+        add_work(m, K_LAYER, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
+      }
+      __syncthreads();
+    }
+    // right-to-left truncation sweep
+    for (int j = r; j > l; --j) {
+      const int Lx = w[j], nn = 2 * w[j + 1];
+      cplx<T> *X = scr<T>(m.T, m.T_cap, s);
+      c64 *Gg = m.G + s * m.G_cap;
+      blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
+      {
+        const Fallback f = fallback(m, s);
+        const bool lp = nn <= kLdsPairs;
+        int *pos = lp ? reinterpret_cast<int *>(lds + kPos) : f.pos;
+        int *pp = lp ? reinterpret_cast<int *>(lds + kPp) : f.pp;
+        int *pq = lp ? reinterpret_cast<int *>(lds + kPq) : f.pq;
+        double *pc = lp ? reinterpret_cast<double *>(lds + kPc) : f.pc;
+        double *ps = lp ? reinterpret_cast<double *>(lds + kPs) : f.ps;
+        c64 *pe = lp ? reinterpret_cast<c64 *>(lds + kPe) : f.pe;
+        c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
+        if (nn <= kLdsEigN) {                 // rotate in LDS, write the sorted vectors back
+          c64 *Gl = reinterpret_cast<c64 *>(lds);
+          blk_copy<double, NT>(Gl, Gg, nn * nn);
+          Gw = Gl;
+          Vw = Gl + kLdsEigN * kLdsEigN;
+        }
+        jacobi_block<NT>(nn, Gw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, &sweeps,
+                         sizeof(T) == 8 ? 1e-18 : 1e-16, sizeof(T) == 8 ? 1e-15 : 1e-13);
+        if (tid == 0) {
+          const double f64 = gemm_flops(nn, nn, Lx) + 36.0 * nn * nn * (double)nn;
+          add_work(m, K_LAYER, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
+          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
+          if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)sweeps);
+        }
+      }
+      cplx<T> *Vt = scr<T>(m.Vt, m.Vt_cap, s);
+      const int k = select_body<T, NT>(m, s, j, Vt);
+      cplx<T> *Nn = scr<T>(m.N, m.N_cap, s);
+      blk_gemm<T, T, T, T, NT>(Lx, k, nn, X, nn, 0, Vt, k, 0, Nn, k, lds);
+      const int M = 2 * w[j - 1];
+      blk_gemm<T, T, T, T, NT>(M, k, Lx, wslot<T>(m, j - 1, s), Lx, 0, Nn, k, 0, X, k, lds);
+      if (tid == 0) {
+        w[j] = k;
+        add_work(m, K_LAYER, gemm_flops(Lx, k, nn) + gemm_flops(M, k, Lx),
+                 (double)sizeof(cplx<T>) * ((double)Lx * nn + (double)nn * k + 2.0 * Lx * k + (double)M * Lx + (double)M * k));
+      }
+      __syncthreads();
+    }
+    finish_body<T, NT>(m, s, l, scr<T>(m.T, m.T_cap, s));
+    c = l;
+  }
+}
+
+template <typename T, int NT>
+void launch_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
+                  const double *d_theta, int64_t stride, const RotLayer &L, hipStream_t st) {
+  KLAUNCH(K_LAYER, (k_layer<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT), st, m, d_pbits, d_psgn, W, SW,
+          d_theta, stride, L);
+}
+
+}  // namespace
+
+size_t layer_fallback_bytes(int chi) {
+  const size_t rows = 4 * (size_t)chi + 2, P = 2 * (size_t)chi + 2;
+  return rows * sizeof(c64) + (P / 2 + 1) * sizeof(c64) + 2 * rows * sizeof(double) +
+         2 * (P / 2 + 1) * sizeof(double) + (P + 2) * sizeof(int) + 2 * (P / 2 + 1) * sizeof(int) + 64;
+}
+
+template <typename T>
+void mps_rot_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
+                   const double *d_theta, int64_t stride, const RotLayer &L, int nt, hipStream_t st) {
+  if (nt == 64) launch_layer<T, 64>(m, d_pbits, d_psgn, W, SW, d_theta, stride, L, st);
+  else if (nt == 128) launch_layer<T, 128>(m, d_pbits, d_psgn, W, SW, d_theta, stride, L, st);
+  else launch_layer<T, 256>(m, d_pbits, d_psgn, W, SW, d_theta, stride, L, st);
+}
+
+template <typename T>
+hipError_t layer_prepare() {
+  hipError_t e = hipSuccess;
+  const void *fs[3] = {(const void *)k_layer<T, 64>, (const void *)k_layer<T, 128>, (const void *)k_layer<T, 256>};
+  const int nts[3] = {64, 128, 256};
+  for (int i = 0; i < 3; ++i) {
+    hipError_t e2 = hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(nts[i]));
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
+}
+
+template void mps_rot_layer<float>(const MpsDev &, const uint64_t *, const uint64_t *, int, int,
+                                   const double *, int64_t, const RotLayer &, int, hipStream_t);
+template void mps_rot_layer<double>(const MpsDev &, const uint64_t *, const uint64_t *, int, int,
+                                    const double *, int64_t, const RotLayer &, int, hipStream_t);
+template hipError_t layer_prepare<float>();
+template hipError_t layer_prepare<double>();

@@ -1,0 +1,471 @@
+// Block-level dense linear algebra of the compression step (Sec. IV.B),
+// shared by the per-step kernels (mps.hip) and the fused per-shot layer
+// kernel (layer.hip).  Every routine runs on one thread block of NT threads
+// (NT = 64, 128 or 256) and works on one shot's matrices; barriers are block
+// barriers only.  Staging buffers are passed in explicitly so that a caller
+// can overlay them in one dynamic LDS region.
+#pragma once
+
+#include "common.h"
+
+#include <math.h>
+
+namespace stnk {
+
+constexpr int GT = 32;           // GEMM tile (GT x GT outputs)
+constexpr int GK = 16;           // GEMM k-step
+
+// ------------------------------------------------------------ accessors
+template <typename T>
+__device__ inline cplx<T> *slot(const MpsDev &m, int j, int s) {
+  return reinterpret_cast<cplx<T> *>(m.mps) + m.site_off[j] + (int64_t)s * m.site_cap[j];
+}
+template <typename T>
+__device__ inline cplx<T> *wslot(const MpsDev &m, int j, int s) {
+  return reinterpret_cast<cplx<T> *>(m.ws) + m.ws_off[j] + (int64_t)s * m.ws_cap[j];
+}
+template <typename T>
+__device__ inline cplx<T> *scr(void *base, int64_t cap, int s) {
+  return reinterpret_cast<cplx<T> *>(base) + (int64_t)s * cap;
+}
+__device__ inline int *bnd(const MpsDev &m, int s) { return m.bond + (size_t)s * (m.n + 1); }
+__device__ inline int *wbd(const MpsDev &m, int s) { return m.wb + (size_t)s * (m.n + 1); }
+__device__ inline int *auxp(const MpsDev &m, int s) { return m.aux + (size_t)s * 8; }
+
+// Algorithmic work of one launch for one shot, added by a single thread.
+__device__ inline void add_work(const MpsDev &m, int cls, double flops, double bytes) {
+  if (m.prof) {
+    atomicAdd(&m.work[2 * cls], flops);
+    atomicAdd(&m.work[2 * cls + 1], bytes);
+  }
+}
+__device__ inline double gemm_flops(double M, double N, double K) { return 8.0 * M * N * K; }
+// Householder QR of an m x n complex matrix with p = min(m, n) reflectors,
+// R plus the explicit m x p Q: 4x the real counts 2mnp - (m+n)p^2 + 2p^3/3
+// for R and 2mp^2 - (m+p)p^2 + 2p^3/3 for Q, times two for multiply-add.
+__device__ inline double qr_flops(double m, double n) {
+  double p = m < n ? m : n;
+  double r = 2 * m * n * p - (m + n) * p * p + 2.0 / 3.0 * p * p * p;
+  double q = 2 * m * p * p - (m + p) * p * p + 2.0 / 3.0 * p * p * p;
+  return 8.0 * (r + q);
+}
+
+// ------------------------------------------------------------ reductions
+// Sum / max over the block; every thread receives the result.
+template <int NT, typename V>
+__device__ V bsum(V v) {
+  __shared__ V red[NT / 64 > 0 ? NT / 64 : 1];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if constexpr (NT == 64) {
+    return v;
+  } else {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    V tot = 0;
+    for (int i = 0; i < NT / 64; ++i) tot += red[i];
+    return tot;
+  }
+}
+
+template <int NT>
+__device__ double bmax(double v) {
+  __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if constexpr (NT == 64) {
+    return v;
+  } else {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double tot = red[0];
+    for (int i = 1; i < NT / 64; ++i) tot = fmax(tot, red[i]);
+    return tot;
+  }
+}
+
+// ------------------------------------------------------------------ GEMM
+// Thread grid TY x TX over a GT x GT tile; each thread owns (GT/TY) x (GT/TX)
+// outputs, strided so that a row of threads reads consecutive columns.
+template <int NT> struct TileShape;
+template <> struct TileShape<64> { static constexpr int TY = 8, TX = 8; };
+template <> struct TileShape<128> { static constexpr int TY = 16, TX = 8; };
+template <> struct TileShape<256> { static constexpr int TY = 16, TX = 16; };
+
+template <typename ACC>
+struct GemmStage {
+  static constexpr size_t bytes = sizeof(cplx<ACC>) * (GT * (GK + 1) + GK * (GT + 1));
+};
+
+// One GT x GT tile of C = op(A) op(B).
+//   opA = 0: A is M x K (lda);  opA = 1: A is K x M and op(A) = A^H.
+//   opB = 0: B is K x N (ldb);  opB = 1: B is N x K and op(B) = B^H.
+// stage: GemmStage<ACC>::bytes of LDS.
+template <typename TA, typename TB_, typename TC, typename ACC, int NT>
+__device__ void gemm_tile(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
+                          const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, int tm,
+                          int tn, void *stage) {
+  constexpr int TY = TileShape<NT>::TY, TX = TileShape<NT>::TX;
+  constexpr int RY = GT / TY, RX = GT / TX;
+  cplx<ACC> *As = reinterpret_cast<cplx<ACC> *>(stage);          // [GT][GK + 1]
+  cplx<ACC> *Bs = As + GT * (GK + 1);                              // [GK][GT + 1]
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const int row0 = tm * GT, col0 = tn * GT;
+  cplx<ACC> acc[RY][RX];
+  for (int i = 0; i < RY; ++i)
+    for (int j = 0; j < RX; ++j) acc[i][j] = mk<ACC>(0, 0);
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int e = tid; e < GT * GK; e += NT) {
+      int mi = e / GK, ki = e % GK;
+      int m = row0 + mi, k = k0 + ki;
+      cplx<ACC> v = mk<ACC>(0, 0);
+      if (m < M && k < K) v = opA ? cj(cvt<ACC>(A[(size_t)k * lda + m])) : cvt<ACC>(A[(size_t)m * lda + k]);
+      As[mi * (GK + 1) + ki] = v;
+    }
+    for (int e = tid; e < GT * GK; e += NT) {
+      int ki = e / GT, ni = e % GT;
+      int n = col0 + ni, k = k0 + ki;
+      cplx<ACC> v = mk<ACC>(0, 0);
+      if (n < N && k < K) v = opB ? cj(cvt<ACC>(B[(size_t)n * ldb + k])) : cvt<ACC>(B[(size_t)k * ldb + n]);
+      Bs[ki * (GT + 1) + ni] = v;
+    }
+    __syncthreads();
+    const int kend = K - k0 < GK ? K - k0 : GK;
+    for (int kk = 0; kk < kend; ++kk) {
+      cplx<ACC> a[RY], b[RX];
+      for (int i = 0; i < RY; ++i) a[i] = As[(ty + TY * i) * (GK + 1) + kk];
+      for (int j = 0; j < RX; ++j) b[j] = Bs[kk * (GT + 1) + tx + TX * j];
+      for (int i = 0; i < RY; ++i)
+        for (int j = 0; j < RX; ++j) acc[i][j] = acc[i][j] + a[i] * b[j];
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < RY; ++i)
+    for (int j = 0; j < RX; ++j) {
+      int m = row0 + ty + TY * i, n = col0 + tx + TX * j;
+      if (m < M && n < N) C[(size_t)m * ldc + n] = cvt<TC>(acc[i][j]);
+    }
+}
+
+// All tiles of a product by the calling block (tiles t0, t0 + dt, ...).
+template <typename TA, typename TB_, typename TC, typename ACC, int NT>
+__device__ void gemm_tiles(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
+                           const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, int t0,
+                           int dt, void *stage) {
+  const int ntm = (M + GT - 1) / GT, ntn = (N + GT - 1) / GT;
+  for (int t = t0; t < ntm * ntn; t += dt)
+    gemm_tile<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, t / ntn, t % ntn, stage);
+}
+
+// ----------------------------------------------------- Householder QR
+// In place on A (m x nc, ld = nc), p = min(m, nc) reflectors.  Writes R
+// (p x nc, ld = nc, zero below the diagonal) to Rd and the explicit Q
+// (m x p) to Qd, either as an m x p matrix (qt = 0) or conjugate-transposed
+// as a p x m matrix (qt = 1).
+// Scratch: vs (m complex doubles), vd (2p doubles), wp (NT complex doubles).
+// The column updates split the block into CL column lanes x G row groups
+// (CL = smallest power of two covering the remaining columns), so narrow
+// trailing matrices still keep every thread busy.
+template <int NT>
+__device__ inline void col_split(int ncols, int &CL, int &G) {
+  int cl = 1;
+  while (cl < ncols && cl < NT) cl <<= 1;
+  CL = cl;
+  G = NT / cl;
+}
+
+// A[i][j] -= vs[i] * 2 (vs^H A)[j] for rows i >= k, columns j in [j0, j1).
+template <typename T, int NT>
+__device__ void reflect_cols(int m, int nc, int k, int j0, int j1, cplx<T> *A, const c64 *vs,
+                             c64 *wp) {
+  const int tid = threadIdx.x;
+  int CL, G;
+  col_split<NT>(j1 - j0, CL, G);
+  const int jj = tid % CL, g = tid / CL;
+  for (int jb = j0; jb < j1; jb += CL) {
+    const int j = jb + jj;
+    c64 w = mk<double>(0, 0);
+    if (j < j1)
+      for (int i = k + g; i < m; i += G) w = w + cj(vs[i]) * cvt<double>(A[(size_t)i * nc + j]);
+    wp[tid] = w;
+    __syncthreads();
+    if (j < j1) {
+      c64 wt = mk<double>(0, 0);
+      for (int gg = 0; gg < G; ++gg) wt = wt + wp[gg * CL + jj];
+      wt = 2.0 * wt;
+      for (int i = k + g; i < m; i += G) {
+        c64 a = cvt<double>(A[(size_t)i * nc + j]) - vs[i] * wt;
+        A[(size_t)i * nc + j] = cvt<T>(a);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int NT>
+__device__ void qr_block(int m, int nc, cplx<T> *A, cplx<T> *Qd, int qt, cplx<T> *Rd, c64 *vs,
+                         double *vd, c64 *wp) {
+  using C = cplx<T>;
+  const int p = m < nc ? m : nc;
+  const int tid = threadIdx.x;
+  for (int k = 0; k < p; ++k) {
+    // Norms and the phase of x0 are formed from double copies: squaring a
+    // float below ~1e-19 lands in the denormal range, and an inexact |x0|
+    // would leave x0/|x0| off the unit circle, so H = I - 2 v v^H would stop
+    // being unitary.
+    double part = 0;
+    for (int i = k + tid; i < m; i += NT) part += norm2(cvt<double>(A[(size_t)i * nc + k]));
+    const double xn2 = bsum<NT>(part);
+    const C x0 = A[(size_t)k * nc + k];
+    const double ax0 = hypot((double)x0.x, (double)x0.y);
+    const double xn = sqrt(xn2);
+    const c64 ph = ax0 > 0 ? mk<double>(x0.x / ax0, x0.y / ax0) : mk<double>(1, 0);
+    const c64 alpha = mk<double>(-ph.x * xn, -ph.y * xn);
+    // v = x - alpha e1, |v|^2 = |x|^2 - |x0|^2 + |x0 - alpha|^2 = 2 |x| (|x| + |x0|)
+    const double vn2 = 2.0 * xn * (xn + ax0);
+    const double inv = vn2 > 0 ? 1.0 / sqrt(vn2) : 0.0;
+    for (int i = k + tid; i < m; i += NT) {
+      c64 xi = cvt<double>(A[(size_t)i * nc + k]);
+      if (i == k) xi = xi - alpha;
+      vs[i] = inv * xi;
+    }
+    __syncthreads();
+    if (inv > 0 && k + 1 < nc) reflect_cols<T, NT>(m, nc, k, k + 1, nc, A, vs, wp);
+    if (tid == 0) {
+      vd[2 * k] = vs[k].x;
+      vd[2 * k + 1] = vs[k].y;
+      A[(size_t)k * nc + k] = cvt<T>(inv > 0 ? alpha : cvt<double>(x0));
+    }
+    for (int i = k + 1 + tid; i < m; i += NT) A[(size_t)i * nc + k] = cvt<T>(vs[i]);
+    __syncthreads();
+  }
+  for (int e = tid; e < p * nc; e += NT) {
+    int i = e / nc, j = e % nc;
+    Rd[e] = j >= i ? A[(size_t)i * nc + j] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  // Q = H_0 ... H_{p-1} [I; 0], accumulated backwards in A's first p columns
+  for (int k = p - 1; k >= 0; --k) {
+    for (int i = k + tid; i < m; i += NT)
+      vs[i] = i == k ? mk<double>(vd[2 * k], vd[2 * k + 1]) : cvt<double>(A[(size_t)i * nc + k]);
+    __syncthreads();
+    for (int i = k + tid; i < m; i += NT) A[(size_t)i * nc + k] = mk<T>(i == k ? 1 : 0, 0);
+    for (int j = k + 1 + tid; j < p; j += NT) A[(size_t)k * nc + j] = mk<T>(0, 0);
+    __syncthreads();
+    reflect_cols<T, NT>(m, nc, k, k, p, A, vs, wp);
+  }
+  for (int e = tid; e < m * p; e += NT) {
+    int i = e / p, j = e % p;
+    C q = A[(size_t)i * nc + j];
+    if (qt)
+      Qd[(size_t)j * m + i] = cj(q);
+    else
+      Qd[e] = q;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------ Jacobi eigen-solve (FP64)
+// Hermitian nn x nn matrix G (ld nn) -> eigenvalues ev (descending) and the
+// matching eigenvectors as columns of Vout (ld nn).  Parallel cyclic Jacobi:
+// each round rotates nn/2 disjoint index pairs in the round-robin (circle)
+// order -- index 0 fixed, the others shifted by one place per round; the
+// 2x2 block [[a, c], [c*, b]] is diagonalised by U = diag(1, e^{-i phi}) R
+// with c = |c| e^{i phi} and R the real symmetric Jacobi rotation.
+// Scratch: pos (nn + 1 ints), pp/pq (nn/2 + 1 ints), pc/ps (nn/2 + 1
+// doubles), pe (nn/2 + 1 complex doubles).
+template <int NT>
+__device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int *err, int *pos,
+                             double *pc, double *ps, c64 *pe, int *pp, int *pq, int *sweeps_out,
+                             double abs_tol, double rel_tol) {
+  const int tid = threadIdx.x;
+  const int P = nn + (nn & 1);
+  for (int e = tid; e < nn * nn; e += NT) V[e] = mk<double>((e / nn) == (e % nn) ? 1.0 : 0.0, 0);
+  // The Gram matrix is positive semi-definite, so its trace bounds every
+  // eigenvalue and is invariant under the rotations.  An entry G_pq is
+  // negligible when |G_pq| <= max(abs_tol tr, rel_tol sqrt(G_pp G_qq)): the
+  // relative part keeps small kept eigenvalues from mixing with the (near)
+  // null space, the absolute floor stops at the rounding level of the Gram.
+  double trp = 0;
+  for (int i = tid; i < nn; i += NT) trp += G[(size_t)i * nn + i].x;
+  const double tr = bsum<NT>(trp);
+  __syncthreads();
+  const double afl = abs_tol * tr;
+  const int max_sweeps = 60;
+  bool converged = nn <= 1 || !(tr > 0);
+  int sweeps_done = 0;
+  double last_off = 0;
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    for (int rnd = 0; rnd < P - 1; ++rnd) {
+      for (int i = tid; i < P / 2; i += NT) {
+        int p = i == 0 ? 0 : 1 + ((i - 1 - rnd) % (P - 1) + (P - 1)) % (P - 1);
+        int q = 1 + ((P - 2 - i - rnd) % (P - 1) + (P - 1)) % (P - 1);
+        if (p > q) { int t = p; p = q; q = t; }
+        double cs = 1, sn = 0;
+        c64 eph = mk<double>(1, 0);
+        if (q < nn) {
+          c64 c = G[(size_t)p * nn + q];
+          double h = sqrt(norm2(c));
+          double a = G[(size_t)p * nn + p].x, b = G[(size_t)q * nn + q].x;
+          if (h > afl && h > rel_tol * sqrt(fabs(a * b))) {
+            eph = mk<double>(c.x / h, c.y / h);
+            double tau = (b - a) / (2 * h);
+            double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1 + tau * tau));
+            cs = 1 / sqrt(1 + t * t);
+            sn = t * cs;
+          }
+        }
+        pp[i] = p; pq[i] = q; pc[i] = cs; ps[i] = sn; pe[i] = eph;
+      }
+      __syncthreads();
+      // rows p, q <- U^H rows
+      for (int e = tid; e < (P / 2) * nn; e += NT) {
+        int i = e / nn, col = e % nn;
+        if (ps[i] == 0) continue;
+        int p = pp[i], q = pq[i];
+        c64 gp = G[(size_t)p * nn + col], gq = G[(size_t)q * nn + col];
+        double cs = pc[i], sn = ps[i];
+        c64 eq = pe[i] * gq;
+        G[(size_t)p * nn + col] = cs * gp - sn * eq;
+        G[(size_t)q * nn + col] = sn * gp + cs * eq;
+      }
+      __syncthreads();
+      // columns p, q <- cols U (and the same for V)
+      for (int e = tid; e < (P / 2) * nn; e += NT) {
+        int i = e / nn, row = e % nn;
+        if (ps[i] == 0) continue;
+        int p = pp[i], q = pq[i];
+        double cs = pc[i], sn = ps[i];
+        c64 ec = cj(pe[i]);
+        c64 gp = G[(size_t)row * nn + p], gq = ec * G[(size_t)row * nn + q];
+        G[(size_t)row * nn + p] = cs * gp - sn * gq;
+        G[(size_t)row * nn + q] = sn * gp + cs * gq;
+        c64 vp = V[(size_t)row * nn + p], vq = ec * V[(size_t)row * nn + q];
+        V[(size_t)row * nn + p] = cs * vp - sn * vq;
+        V[(size_t)row * nn + q] = sn * vp + cs * vq;
+      }
+      __syncthreads();
+    }
+    double off = 0, viol = 0;
+    for (int e = tid; e < nn * nn; e += NT) {
+      const int p = e / nn, q = e % nn;
+      if (p == q) continue;
+      const double h = sqrt(norm2(G[e]));
+      off = fmax(off, h);
+      if (h > afl && h > rel_tol * sqrt(fabs(G[(size_t)p * nn + p].x * G[(size_t)q * nn + q].x))) viol = 1;
+    }
+    off = bmax<NT>(off);
+    viol = bmax<NT>(viol);
+    last_off = off;
+    converged = viol == 0;
+    sweeps_done = sweep + 1;
+    __syncthreads();
+  }
+  if (sweeps_out && tid == 0) *sweeps_out = sweeps_done;
+  if (!converged && tid == 0 && last_off > 1e-10 * tr) atomicOr(err, STN_ERR_EIGEN);
+  // sort descending: rank of each eigenvalue (ties by index)
+  for (int i = tid; i < nn; i += NT) {
+    double li = G[(size_t)i * nn + i].x;
+    int rank = 0;
+    for (int j = 0; j < nn; ++j) {
+      double lj = G[(size_t)j * nn + j].x;
+      rank += (lj > li) || (lj == li && j < i);
+    }
+    ev[rank] = li;
+    pos[i] = rank;
+  }
+  __syncthreads();
+  for (int e = tid; e < nn * nn; e += NT) {
+    int row = e / nn, col = e % nn;
+    Vout[(size_t)row * nn + pos[col]] = V[e];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ truncation
+// Keep k' = min(chi_max, #{lambda_i > eps sum lambda}, 2^min(j, n-j)) largest
+// (at least 1); the discarded weight updates the fidelity; Vt = V[:, :k']
+// (nn x k'); site j <- Vt^H as (k', 2, wb[j+1]); bond[j] = k',
+// bond[j+1] = wb[j+1].  V (sorted eigenvectors) and ev are read from G, ev.
+template <typename T, int NT>
+__device__ int select_body(const MpsDev &m, int s, int j, cplx<T> *Vt) {
+  int *w = wbd(m, s);
+  const int nn = 2 * w[j + 1];
+  const double *ev = m.ev + s * m.ev_cap;
+  __shared__ int kk;
+  double part = 0;
+  for (int i = threadIdx.x; i < nn; i += NT) part += fmax(ev[i], 0.0);
+  const double tot = bsum<NT>(part);
+  int cnt = 0;
+  for (int i = threadIdx.x; i < nn; i += NT) cnt += ev[i] > m.eps_cut * tot;
+  cnt = bsum<NT>(cnt);
+  if (threadIdx.x == 0) {
+    int k = cnt < m.chi ? cnt : m.chi;
+    const int e = j < m.n - j ? j : m.n - j;           // physical bound 2^min(j, n-j)
+    if (e < 30 && k > (1 << e)) k = 1 << e;
+    if (k < 1) k = 1;
+    double disc = 0;
+    for (int i = k; i < nn; ++i) disc += fmax(ev[i], 0.0);
+    const double wgt = tot > 0 ? disc / tot : 0.0;
+    m.fid[s] *= (1.0 - wgt);
+    if (!(tot == tot) || isinf(tot)) atomicOr(m.err, STN_ERR_NUMERIC);
+    kk = k;
+    auxp(m, s)[2] = k;
+    auxp(m, s)[3] = w[j];          // L, read by the Q N product while wb[j] changes
+  }
+  __syncthreads();
+  const int k = kk;
+  const c64 *V = m.G + s * m.G_cap;
+  cplx<T> *site = slot<T>(m, j, s);
+  for (int e = threadIdx.x; e < nn * k; e += NT) {
+    int i = e / k, c = e % k;
+    cplx<T> v = cvt<T>(V[(size_t)i * nn + c]);
+    Vt[e] = v;
+    site[(size_t)c * nn + i] = cj(v);
+  }
+  if (threadIdx.x == 0) {
+    bnd(m, s)[j] = k;
+    bnd(m, s)[j + 1] = w[j + 1];
+  }
+  __syncthreads();
+  return k;
+}
+
+// Centre at l: normalise X (wb[l], 2, wb[l+1]) in FP64 into slot l;
+// bond[l+1] = wb[l+1]; nrm[s] = the squared norm before normalisation.
+template <typename T, int NT>
+__device__ void finish_body(const MpsDev &m, int s, int l, const cplx<T> *X) {
+  int *w = wbd(m, s);
+  const int cnt = w[l] * 2 * w[l + 1];
+  double part = 0;
+  for (int e = threadIdx.x; e < cnt; e += NT) part += norm2(cvt<double>(X[e]));
+  const double n2 = bsum<NT>(part);
+  if (!(n2 > 0) || isinf(n2)) {
+    if (threadIdx.x == 0) atomicOr(m.err, STN_ERR_NUMERIC);
+    __syncthreads();
+    return;
+  }
+  const double inv = 1.0 / sqrt(n2);
+  cplx<T> *out = slot<T>(m, l, s);
+  for (int e = threadIdx.x; e < cnt; e += NT) out[e] = cvt<T>(inv * cvt<double>(X[e]));
+  if (threadIdx.x == 0) {
+    bnd(m, s)[l + 1] = w[l + 1];
+    m.nrm[s] = n2;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------- Pauli site operators
+__device__ inline void site_op(int x, int z, c64 *o) {
+  // i^(xz) X^x Z^z
+  if (!x && !z) { o[0] = mk<double>(1, 0); o[1] = mk<double>(0, 0); o[2] = mk<double>(0, 0); o[3] = mk<double>(1, 0); }
+  if (!x && z) { o[0] = mk<double>(1, 0); o[1] = mk<double>(0, 0); o[2] = mk<double>(0, 0); o[3] = mk<double>(-1, 0); }
+  if (x && !z) { o[0] = mk<double>(0, 0); o[1] = mk<double>(1, 0); o[2] = mk<double>(1, 0); o[3] = mk<double>(0, 0); }
+  if (x && z) { o[0] = mk<double>(0, 0); o[1] = mk<double>(0, -1); o[2] = mk<double>(0, 1); o[3] = mk<double>(0, 0); }
+}
+__device__ inline int bitw(const uint64_t *v, int j) { return (int)((v[j >> 6] >> (j & 63)) & 1ull); }
+
+}  // namespace stnk

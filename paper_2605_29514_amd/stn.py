@@ -41,7 +41,7 @@ _lib = None
 EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn_clifford",
            "stn_rotate", "stn_measure", "stn_logprob", "stn_sync", "stn_get_tableau",
            "stn_get_bonds", "stn_get_site", "stn_center", "stn_profile", "stn_profile_read",
-           "stn_set_site", "stn_set_center", "stn_set_layer_mode"]
+           "stn_set_site", "stn_set_center", "stn_set_layer_mode", "stn_set_layer_threads"]
 K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect", "layer"]
 
 
@@ -91,6 +91,8 @@ def load(path: str = LIB_PATH):
     lib.stn_profile_read.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.stn_set_layer_mode.restype = i32
     lib.stn_set_layer_mode.argtypes = [vp, i32]
+    lib.stn_set_layer_threads.restype = i32
+    lib.stn_set_layer_threads.argtypes = [vp, i32]
     _lib = lib
     return lib
 
@@ -120,7 +122,7 @@ class Simulator:
 
     def __init__(self, n_qubits: int, n_shots: int, chi_max: int, precision: str = "fp32",
                  eps_cut: Optional[float] = None, device: str = "cuda:0", poison: bool = False,
-                 layer_mode: int = 0):
+                 layer_mode: int = 0, layer_threads: int = 0):
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -150,6 +152,8 @@ class Simulator:
         self.SW = (n_shots + 63) // 64
         if layer_mode:
             self.set_layer_mode(layer_mode)
+        if layer_threads:
+            self.set_layer_threads(layer_threads)
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -276,6 +280,10 @@ class Simulator:
         """0 automatic, 1 per-step kernels, 2 fused per-shot layer kernel."""
         self._check(self.lib.stn_set_layer_mode(self.ctx, int(mode)))
 
+    def set_layer_threads(self, threads: int):
+        """Threads per shot of the fused layer kernel (64, 128 or 256)."""
+        self._check(self.lib.stn_set_layer_threads(self.ctx, int(threads)))
+
 
 # ----------------------------------------------------------------- circuits
 def prepare(circ, device="cuda:0", forced: Optional[np.ndarray] = None):
@@ -329,12 +337,13 @@ def run_prepared(sim: Simulator, ops, start: int = 0, stop: Optional[int] = None
 
 def run_circuit(circ, chi_max: int, precision: str = "fp32", eps_cut: Optional[float] = None,
                 device: str = "cuda:0", forced: Optional[np.ndarray] = None, sim: Optional[Simulator] = None,
-                layer_mode: int = 0):
+                layer_mode: int = 0, layer_threads: int = 0):
     """Simulates every shot of a workload Circuit on the GPU.  Returns a dict
     with records [S, M] uint8, prob [S, M], logp [S], trunc_err [S] (numpy)
     and the Simulator (for tableau / MPS inspection)."""
     if sim is None:
-        sim = Simulator(circ.n, circ.n_shots, chi_max, precision, eps_cut, device, layer_mode=layer_mode)
+        sim = Simulator(circ.n, circ.n_shots, chi_max, precision, eps_cut, device, layer_mode=layer_mode,
+                        layer_threads=layer_threads)
     ops = prepare(circ, device, forced)
     res = run_prepared(sim, ops)
     lp, te = sim.logprob()

@@ -61,10 +61,20 @@ def mps_fidelity(sim, shot, omps):
     return 1 - ov
 
 
+def sched(mode):
+    """(layer mode, threads per shot) from a test parameter."""
+    return mode if isinstance(mode, tuple) else (mode, 0)
+
+
+# per-step kernels, fused kernel with one wavefront per shot, fused with 256 threads
+MODES = [(1, 0), (2, 64), (2, 256)]
+
+
 def run_parity(B, circ, chi, prec, shots, *, check_mps=True, tie=None, mode=0):
-    say(f"parity n={circ.n} S={circ.n_shots} chi={chi} {prec} layer mode {mode}")
+    lm, nt = sched(mode)
+    say(f"parity n={circ.n} S={circ.n_shots} chi={chi} {prec} layer mode {lm} threads {nt}")
     eps = EPS[prec]
-    g = B.run_circuit(circ, chi, prec, eps, layer_mode=mode)
+    g = B.run_circuit(circ, chi, prec, eps, layer_mode=lm, layer_threads=nt)
     ores = {s: ostn.run_shot(circ, s, chi_max=chi, eps_cut=eps) for s in shots}
     tie = tie if tie is not None else (1e-9 if prec == "fp64" else 1e-4)
     cond = [s for s in shots if ores[s].cut_sensitivity <= MAX_SENS[prec]]
@@ -83,7 +93,7 @@ def run_parity(B, circ, chi, prec, shots, *, check_mps=True, tie=None, mode=0):
     # probabilities with the oracle's records forced on the GPU side
     forced = np.array([ores[s].record if s in ores else g["records"][s]
                        for s in range(circ.n_shots)], np.uint8)
-    gf = B.run_circuit(circ, chi, prec, eps, forced=forced, layer_mode=mode)
+    gf = B.run_circuit(circ, chi, prec, eps, forced=forced, layer_mode=lm, layer_threads=nt)
     worst = 0.0
     for s in shots:
         po = np.array(ores[s].prob)
@@ -136,14 +146,14 @@ def test_random_gate_set_tableau(B):
     run_parity(B, circ, 64, "fp64", range(5))
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_d3_crosstalk_no_truncation(B, prec, mode):
     circ = W.memory_circuit(3, 3, 8, seed=11, theta_nn=0.05, p=0.0)
     run_parity(B, circ, 64, prec, range(8), mode=mode)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_d3_noise_nnn_hard_truncation(B, prec, mode):
     """chi_max = 4 binds hard (a few % of the weight discarded per shot): the
@@ -161,25 +171,27 @@ def test_d3_noise_nnn_truncating(B, prec, chi):
     run_parity(B, circ, chi, prec, range(6))
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", MODES)
 def test_d5_first_round_fp32(B, mode):
     circ = W.memory_circuit(5, 1, 8, seed=21, theta_law="per_coupling", nnn=True, p=1e-3)
     run_parity(B, circ, 256, "fp32", range(4), mode=mode)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", MODES)
 def test_per_shot_theta(B, mode):
     circ = W.memory_circuit(3, 2, 6, seed=31, theta_law="per_shot", theta_range=(0.01, 0.08), nnn=True)
     run_parity(B, circ, 16, "fp64", range(6), mode=mode)
 
 
+@pytest.mark.parametrize("threads", [64, 128, 256])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_layer_modes_agree(B, prec):
-    """The fused per-shot layer kernel and the per-step kernels give the same
-    records and probabilities (up to rounding order) on 96 shots."""
+def test_layer_modes_agree(B, prec, threads):
+    """The fused per-shot layer kernel (any block size) and the per-step
+    kernels give the same records and probabilities (up to rounding order)
+    on 96 shots."""
     circ = W.memory_circuit(3, 2, 96, seed=43, theta_law="per_coupling", nnn=True, p=0.01)
     a = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=1)
-    b = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=2)
+    b = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=2, layer_threads=threads)
     same = np.all(a["records"] == b["records"], axis=1)
     assert same.mean() > 0.95
     rel = np.abs(a["prob"][same] - b["prob"][same]) / a["prob"][same]
@@ -219,11 +231,12 @@ def test_bad_arguments(B):
     sim.sync()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", MODES)
 def test_repeat_is_bit_identical(B, mode):
+    lm, nt = sched(mode)
     circ = W.memory_circuit(3, 2, 16, seed=41, theta_nn=0.06, p=0.01)
-    a = B.run_circuit(circ, 8, "fp32", layer_mode=mode)
-    b = B.run_circuit(circ, 8, "fp32", layer_mode=mode)
+    a = B.run_circuit(circ, 8, "fp32", layer_mode=lm, layer_threads=nt)
+    b = B.run_circuit(circ, 8, "fp32", layer_mode=lm, layer_threads=nt)
     assert np.array_equal(a["records"], b["records"])
     assert np.array_equal(a["prob"], b["prob"])
     assert np.array_equal(a["sim"].bonds(), b["sim"].bonds())
