@@ -157,6 +157,7 @@ def main():
     ap.add_argument("--profile-all", action="store_true")
     ap.add_argument("--layer-mode", type=int, default=0, help="0 automatic, 1 per-step kernels, 2 fused")
     ap.add_argument("--layer-threads", type=int, default=0, help="threads per shot of the fused kernel")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -189,6 +190,15 @@ def main():
                         layer_threads=args.layer_threads)
     ops = stn.prepare(circ, dev)
     rounds = split_rounds(ops)
+    schedule = {"layer_mode": args.layer_mode, "layer_threads": args.layer_threads, "tuned": False}
+    if args.layer_mode == 0 and args.layer_threads == 0 and not args.no_tune:
+        from paper_2605_29514_amd import tune
+        key = tune.problem_key(torch.cuda.get_device_name(0), circ.n, circ.n_shots, chi, prec, args.config)
+        t = tune.autotune(sim, ops, tune.layers_stop(ops, 2), key=key,
+                          log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+        schedule = {"layer_mode": t["choice"][0], "layer_threads": t["choice"][1], "tuned": True,
+                    "cached": t["cached"], "candidates_ms": t["ms"]}
+        print(f"# autotuned schedule {t['choice']}", file=sys.stderr, flush=True)
     W, K = args.warmup, args.steps
     if W + K > len(rounds):
         print(f"warmup + steps exceeds the {len(rounds)} rounds of the circuit", file=sys.stderr)
@@ -264,7 +274,7 @@ def main():
                                f"{circ.n} qubits, rounds {W + 1}-{W + K} of {cfg['rounds']}",
                    "shots": circ.n_shots, "chi_max": chi, "rotations_timed": n_rot,
                    "max_bond_after": int(bonds.max()), "mean_bond_after": float(bonds.mean()),
-                   "wall_s": wall, "eigen_sweeps": prof["eigen_sweeps"],
+                   "wall_s": wall, "eigen_sweeps": prof["eigen_sweeps"], "schedule": schedule,
                    "class_ms": {c: prof[c]["ms"] for c in classes}},
         "roofline": roof,
         "cpu_baseline": cpu,

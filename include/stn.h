@@ -158,6 +158,13 @@ stn_status stn_get_bonds(stn_ctx *ctx, int32_t *host_bonds);
 stn_status stn_get_site(stn_ctx *ctx, int shot, int site, void *host_buf,
                         size_t bytes, int *dl, int *dr);
 
+/* Returns every shot to the initial state (identity frame, MPS |0...0>,
+ * log P = 0, fidelity 1, error word cleared) with kernel launches only: no
+ * copy, fill or synchronisation, so a caller may capture stn_reset followed
+ * by a whole circuit in a HIP graph and replay it for new batches of shots
+ * (new angles, noise and uniforms written into the same device buffers). */
+stn_status stn_reset(stn_ctx *ctx);
+
 /* Kernel classes for stn_profile / stn_profile_read. */
 enum { STN_K_TABLEAU = 0,  /* tableau gates, rewrite, frame change */
        STN_K_BUILD = 1,    /* bond-2 operator blocks, copies, coefficients */

@@ -6,6 +6,7 @@
 // as the device, to know each step's span [l, r] and whether a measurement
 // needs a frame change before launching.  Every result (signs, bits used by
 // the kernels, the MPS, outcomes, probabilities) is computed on the device.
+#include <algorithm>
 #include <complex>
 #include <cstdio>
 #include <cstring>
@@ -664,6 +665,23 @@ stn_status stn_profile_read(stn_ctx *c, double *ms, double *flops, double *bytes
   if (eig_sweeps) *eig_sweeps = w[2 * K_COUNT];
   if (layer_fp64_flops) *layer_fp64_flops = w[2 * K_COUNT + 1];
   return STN_OK;
+}
+
+stn_status stn_reset(stn_ctx *c) {
+  if (!c) return STN_EINVAL;
+  ProfScope ps(c);
+  launch_tab_reset(c->tab, c->d_err, c->st);
+  if (c->prec == STN_FP64) mps_init<double>(c->mps, c->st);
+  else mps_init<float>(c->mps, c->st);
+  const int n = c->n;
+  std::fill(c->hx.begin(), c->hx.end(), 0);
+  std::fill(c->hz.begin(), c->hz.end(), 0);
+  for (int j = 0; j < n; ++j) {
+    setbit(&c->hx[(size_t)j * c->W], j, 1);
+    setbit(&c->hz[(size_t)(n + j) * c->W], j, 1);
+  }
+  c->center = 0;
+  return check_launch(c);
 }
 
 stn_status stn_sync(stn_ctx *c) {

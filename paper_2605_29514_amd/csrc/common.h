@@ -90,6 +90,7 @@ struct ProgBatch {
 };
 
 
+void launch_tab_reset(const TabDev &t, int *d_err, hipStream_t st);
 void launch_tab_gates(const TabDev &t, const ProgBatch &b, int *d_err, hipStream_t st);
 void launch_tab_noise(const TabDev &t, const uint64_t *d_noise, hipStream_t st);
 void launch_tab_products(const TabDev &t, const ProgBatch &b, uint64_t *d_out_bits,

@@ -192,7 +192,25 @@ __global__ void k_tab_snapshot(TabDev t, int row, uint64_t *snap) {
   for (int w = threadIdx.x; w < t.SW; w += blockDim.x) snap[2 * t.W + w] = t.s[(size_t)row * t.SW + w];
 }
 
+// Identity frame: row j (X_j) has x bit j, row n + j (Z_j) has z bit j, all
+// signs +; also clears the device error word.  One block per row.
+__global__ void k_tab_reset(TabDev t, int *err) {
+  const int row = blockIdx.x;
+  const int q = row < t.n ? row : row - t.n;
+  for (int w = threadIdx.x; w < t.W; w += blockDim.x) {
+    const uint64_t bit = (w == (q >> 6)) ? (1ull << (q & 63)) : 0ull;
+    t.x[(size_t)row * t.W + w] = row < t.n ? bit : 0ull;
+    t.z[(size_t)row * t.W + w] = row < t.n ? 0ull : bit;
+  }
+  for (int w = threadIdx.x; w < t.SW; w += blockDim.x) t.s[(size_t)row * t.SW + w] = 0ull;
+  if (row == 0 && threadIdx.x == 0) *err = 0;
+}
+
 }  // namespace
+
+void launch_tab_reset(const TabDev &t, int *d_err, hipStream_t st) {
+  KLAUNCH(K_TABLEAU, k_tab_reset, dim3(2 * t.n), dim3(64), 0, st, t, d_err);
+}
 
 void launch_tab_gates(const TabDev &t, const ProgBatch &b, int *d_err, hipStream_t st) {
   if (b.ngates <= 0) return;

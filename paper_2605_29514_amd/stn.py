@@ -41,7 +41,7 @@ _lib = None
 EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn_clifford",
            "stn_rotate", "stn_measure", "stn_logprob", "stn_sync", "stn_get_tableau",
            "stn_get_bonds", "stn_get_site", "stn_center", "stn_profile", "stn_profile_read",
-           "stn_set_site", "stn_set_center", "stn_set_layer_mode", "stn_set_layer_threads"]
+           "stn_set_site", "stn_set_center", "stn_set_layer_mode", "stn_set_layer_threads", "stn_reset"]
 K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect", "layer"]
 
 
@@ -92,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.stn_set_layer_mode.restype = i32
     lib.stn_set_layer_mode.argtypes = [vp, i32]
     lib.stn_set_layer_threads.restype = i32
+    lib.stn_reset.restype = i32
+    lib.stn_reset.argtypes = [vp]
     lib.stn_set_layer_threads.argtypes = [vp, i32]
     _lib = lib
     return lib
@@ -122,7 +124,9 @@ class Simulator:
 
     def __init__(self, n_qubits: int, n_shots: int, chi_max: int, precision: str = "fp32",
                  eps_cut: Optional[float] = None, device: str = "cuda:0", poison: bool = False,
-                 layer_mode: int = 0, layer_threads: int = 0):
+                 layer_mode: int = 0, layer_threads: int = 0, stream=None):
+        """stream: torch.cuda.Stream every launch goes to (default: the
+        current stream); a side stream is needed to capture HIP graphs."""
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -132,7 +136,7 @@ class Simulator:
         self.prec = STN_FP64 if precision == "fp64" else STN_FP32
         self.n, self.S, self.chi = n_qubits, n_shots, chi_max
         self.eps_cut = DEFAULT_EPS[self.prec] if eps_cut is None else eps_cut
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.cfg = StnConfig(n_qubits, n_shots, chi_max, self.prec, self.eps_cut,
                              ctypes.c_void_p(self.stream.cuda_stream))
         nbytes = self.lib.stn_workspace_bytes(ctypes.byref(self.cfg))
@@ -211,6 +215,10 @@ class Simulator:
 
     def sync(self):
         self._check(self.lib.stn_sync(self.ctx))
+
+    def reset(self):
+        """Initial state for every shot, by kernel launches only (capturable)."""
+        self._check(self.lib.stn_reset(self.ctx))
 
     def tableau(self):
         """(x [2n, n] bool, z [2n, n] bool, sign [2n, S] bool)."""
@@ -333,6 +341,43 @@ def run_prepared(sim: Simulator, ops, start: int = 0, stop: Optional[int] = None
         elif k == "measure":
             res.append(sim.measure(op[1], op[2], u=None if op[4] is not None else op[3], forced=op[4]))
     return res
+
+
+def capture(sim: Simulator, ops):
+    """Captures stn_reset followed by every prepared op into a HIP graph on
+    the Simulator's (side) stream.  Returns (graph, results): each
+    graph.replay() re-runs the whole circuit for the current contents of the
+    ops' device inputs and rewrites the captured (outcomes, prob) tensors."""
+    import torch
+    if sim.stream == torch.cuda.current_stream(sim.device) and sim.stream.cuda_stream == 0:
+        raise ValueError("graph capture needs a Simulator created on a side stream")
+    sim.stream.wait_stream(torch.cuda.current_stream(sim.device))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=sim.stream):
+        sim.reset()
+        res = run_prepared(sim, ops)
+    return g, res
+
+
+def load_inputs(dst_ops, src_ops):
+    """Copies the per-shot device inputs of src_ops into the tensors of
+    dst_ops (same circuit structure), e.g. a new batch of shots for a
+    captured graph.  Host-side parts (gates, Pauli lists) must agree."""
+    for a, b in zip(dst_ops, src_ops):
+        if a[0] != b[0]:
+            raise ValueError("op sequences differ")
+        if a[0] == "noise":
+            a[1].copy_(b[1])
+        elif a[0] == "rotate":
+            if not np.array_equal(a[1], b[1]) or a[3] != b[3]:
+                raise ValueError("rotation Paulis differ")
+            a[2].copy_(b[2])
+        elif a[0] == "measure":
+            a[3].copy_(b[3])
+            if a[4] is not None:
+                a[4].copy_(b[4])
+        elif a[0] == "gates" and a[1] != b[1]:
+            raise ValueError("gate lists differ")
 
 
 def run_circuit(circ, chi_max: int, precision: str = "fp32", eps_cut: Optional[float] = None,

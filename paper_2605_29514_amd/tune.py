@@ -1,0 +1,115 @@
+"""Launch-shape autotuner for the rotation layers.
+
+The library offers two schedules for a chunk of rotations -- per-step
+kernels with many blocks per product, or the fused per-shot layer kernel --
+and three block sizes for the fused kernel (64, 128, 256 threads per shot).
+Which one is fastest depends on the shot count, the bond dimensions the
+circuit reaches and the precision, so it is measured, not guessed: each
+candidate runs the same prefix of the real workload on the real Simulator
+(state reset before and after with stn_reset, so no second workspace is
+needed), timed with HIP events on the Simulator's stream, and the fastest is
+kept.  Results are cached per (device, problem) key in a JSON file.
+
+All candidates compute the same results up to rounding order (the GPU parity
+tests run every one of them against the oracle).
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+# (layer mode, threads per shot): 1 = per-step kernels, 2 = fused kernel
+CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 0), (2, 64), (2, 128), (2, 256))
+
+
+def cache_path() -> str:
+    return os.environ.get("STN_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2605_29514_amd", "tune.json"))
+
+
+def problem_key(device_name: str, n: int, shots: int, chi: int, precision: str, workload: str) -> str:
+    return f"{device_name}|n={n}|S={shots}|chi={chi}|{precision}|{workload}"
+
+
+def load_cache(path: Optional[str] = None) -> Dict[str, dict]:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store_cache(key: str, entry: dict, path: Optional[str] = None) -> None:
+    path = path or cache_path()
+    data = load_cache(path)
+    data[key] = entry
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def pick(timings: Dict[Tuple[int, int], float]) -> Tuple[int, int]:
+    """Fastest candidate; ties go to the earlier entry of CANDIDATES."""
+    order = {c: i for i, c in enumerate(CANDIDATES)}
+    return min(timings, key=lambda c: (timings[c], order.get(c, len(order))))
+
+
+def apply(sim, choice: Sequence[int]) -> None:
+    mode, threads = int(choice[0]), int(choice[1])
+    sim.set_layer_mode(mode)
+    if threads:
+        sim.set_layer_threads(threads)
+
+
+def autotune(sim, ops, stop: int, *, key: Optional[str] = None, candidates: Iterable = CANDIDATES,
+             use_cache: bool = True, log=None) -> dict:
+    """Times ops[:stop] (a prefix of the workload, from the initial state) for
+    every candidate on `sim`, leaves `sim` reset to the initial state with the
+    fastest candidate applied, and returns {"choice", "ms", "cached"}."""
+    import torch
+    from . import stn
+    if use_cache and key:
+        hit = load_cache().get(key)
+        if hit and tuple(hit.get("choice", ())) in set(map(tuple, candidates)):
+            apply(sim, hit["choice"])
+            sim.reset()
+            return {"choice": tuple(hit["choice"]), "ms": hit.get("ms"), "cached": True}
+    timings: Dict[Tuple[int, int], float] = {}
+    for cand in candidates:
+        cand = tuple(cand)
+        apply(sim, cand)
+        sim.reset()
+        sim.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(sim.stream)
+        stn.run_prepared(sim, ops, 0, stop)
+        b.record(sim.stream)
+        sim.sync()
+        timings[cand] = a.elapsed_time(b)
+        if log:
+            log(f"autotune {cand}: {timings[cand]:.1f} ms")
+    best = pick(timings)
+    apply(sim, best)
+    sim.reset()
+    sim.sync()
+    ms = {f"{m}/{t}": v for (m, t), v in timings.items()}
+    if key:
+        store_cache(key, {"choice": list(best), "ms": ms})
+    return {"choice": best, "ms": ms, "cached": False}
+
+
+def layers_stop(ops, layers: int = 2) -> int:
+    """Index just past the `layers`-th rotation op of a prepared op list (the
+    autotuning prefix: the first crosstalk layers)."""
+    seen = 0
+    for i, op in enumerate(ops):
+        if op[0] == "rotate":
+            seen += 1
+            if seen == layers:
+                return i + 1
+    return len(ops)

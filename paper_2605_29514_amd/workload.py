@@ -262,8 +262,13 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
                    theta_nn=0.05, nnn: bool = False, theta_triple=None,
                    theta_law: str = "fixed", theta_range=(0.02, 0.10),
                    p: float = 0.0, per_layer_params: bool = False,
-                   random_sign: bool = False, final_readout: bool = True) -> Circuit:
+                   random_sign: bool = False, final_readout: bool = True,
+                   dense_noise: bool = False) -> Circuit:
     """Memory-Z experiment on the rotated code with ZZ(Z) crosstalk.
+
+    dense_noise: emit a noise op at every noise location even when no shot
+    fires there, so that the op sequence does not depend on the seed (one
+    captured graph then serves every batch of shots).
 
     theta_law:
       "fixed"        every NN coupling gets theta_nn, NNN theta_nn/2, triples theta_triple
@@ -314,7 +319,7 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
 
     def add_noise(xz):
         x, z = xz
-        if x.any() or z.any():
+        if dense_noise or x.any() or z.any():
             ops.append({"op": "noise", "x": x, "z": z})
 
     for rnd in range(rounds):
