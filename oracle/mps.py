@@ -74,6 +74,11 @@ class MPS:
         self.center = 0
         self.fidelity = 1.0                    # prod over cuts of (1 - w)
         self.discarded = []                    # per-cut discarded weight w
+        # bookkeeping of the last apply_two_term, read by the gradient oracle:
+        # whether chi_max dropped a value above the relative cut at some cut,
+        # and the norm of the compressed state before renormalisation
+        self.last_truncated = False
+        self.last_norm = 1.0
         # conditioning of the cuts where chi_max binds: s_k^2 / (s_k^2 - s_{k+1}^2)
         # for the last kept value k (inf for an exact tie).  Eq. 8 keeps the
         # largest values but leaves ties at the cut open; a large value means the
@@ -161,10 +166,11 @@ class MPS:
         and renormalise.  o1/o2 map site -> 2x2 matrix (identity if absent)."""
         eye = np.eye(2, dtype=complex)
         self.move_center(l)
+        self.last_truncated = False
         if l == r:
             t = self.A[l]
             self.A[l] = a * _apply_site(o1.get(l, eye), t) + b * _apply_site(o2.get(l, eye), t)
-            self.normalize()
+            self.last_norm = self.normalize()
             return
         # bond-2 operator blocks over the span
         B = {}
@@ -194,6 +200,7 @@ class MPS:
             k = keep_count(s, self.chi_max, self.eps_cut)
             tot = float(np.sum(s.astype(np.float64) ** 2))
             if k < len(s) and s[k] ** 2 > self.eps_cut * tot:
+                self.last_truncated = True
                 gap = float(s[k - 1] ** 2 - s[k] ** 2)
                 sens = float(s[k - 1] ** 2) / gap if gap > 0 else float("inf")
                 self.max_cut_sensitivity = max(self.max_cut_sensitivity, sens)
@@ -204,7 +211,7 @@ class MPS:
             prv = self.A[j - 1]
             self.A[j - 1] = (prv.reshape(-1, prv.shape[2]) @ (u[:, :k] * s[:k])).reshape(prv.shape[0], 2, k)
         self.center = l
-        self.normalize()
+        self.last_norm = self.normalize()
 
     def schmidt_values(self, bond: int) -> np.ndarray:
         """Schmidt values across the cut between sites bond and bond+1."""
