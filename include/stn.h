@@ -165,6 +165,60 @@ stn_status stn_get_site(stn_ctx *ctx, int shot, int site, void *host_buf,
  * (new angles, noise and uniforms written into the same device buffers). */
 stn_status stn_reset(stn_ctx *ctx);
 
+/* ------------------------------------------------------------ gradients
+ * d log P(record) / d theta for every recorded rotation, by an adjoint pass
+ * over a recorded stretch of the circuit.  Objective: J = sum of log p_k
+ * over the recorded measurements (the quantity stn_logprob accumulates).
+ * The rotations exp(-i theta P) are differentiated exactly (Eq. 4); each
+ * truncation that dropped weight above the relative cut (chi_max binding)
+ * is held fixed as the orthogonal projector onto the kept right-Schmidt
+ * subspace of its step, while steps that only removed numerically null
+ * directions count as exact; Clifford gates, noise, frame changes and the
+ * record do not depend on theta.  Usage: stn_checkpoint_save at the start
+ * of each stretch during the forward run; backwards over the stretches:
+ * stn_checkpoint_load, stn_tape_begin, re-issue the stretch's calls with the
+ * recorded outcomes forced, stn_tape_end, stn_backward.  The adjoint state
+ * carries over between stretches (stn_adjoint_zero before the last one). */
+
+/* Device bytes of a tape of up to max_steps rotations + measurements (each
+ * step keeps a snapshot of all shots' MPS slots).  0 for bad arguments. */
+size_t stn_tape_bytes(const stn_ctx *ctx, int max_steps);
+
+/* Starts recording into dev_tape (caller-owned, 256-byte aligned, at least
+ * stn_tape_bytes).  While recording, stn_rotate uses the per-step
+ * schedule.  A stn_rotate / stn_measure call that would exceed max_steps
+ * fails with STN_ENOMEM. */
+stn_status stn_tape_begin(stn_ctx *ctx, void *dev_tape, size_t bytes, int max_steps);
+
+/* Stops recording (snapshots the final state); *n_rotations (may be NULL)
+ * receives the number of rotations recorded.  STN_ESTATE if not recording. */
+stn_status stn_tape_end(stn_ctx *ctx, int *n_rotations);
+
+/* Device bytes of the adjoint state with bond cap chi_adj (1..512); the
+ * adjoint of a chi_max forward needs about 3 chi_max to stay exact. */
+size_t stn_adjoint_bytes(const stn_ctx *ctx, int chi_adj);
+
+/* Places the adjoint state in dev_buf (caller-owned, 256-byte aligned, at
+ * least stn_adjoint_bytes) and sets it to zero.  Synchronises. */
+stn_status stn_adjoint_init(stn_ctx *ctx, void *dev_buf, size_t bytes, int chi_adj);
+
+/* Sets the adjoint state to zero (start of a backward pass). */
+stn_status stn_adjoint_zero(stn_ctx *ctx);
+
+/* Adjoint pass over the closed tape, last step first: writes dJ/dtheta of
+ * the tape's i-th rotation for shot s to dev_grad[s * grad_stride + i]
+ * (grad_stride >= the tape's rotation count unless n_shots == 1) and leaves
+ * the adjoint state at the tape's start for an earlier stretch.
+ * Synchronises; STN_ESTATE without a closed tape or an adjoint state. */
+stn_status stn_backward(stn_ctx *ctx, double *dev_grad, int64_t grad_stride);
+
+/* Checkpoint of the whole forward state (MPS, tableau, log P, fidelity and
+ * the host-side copy of the shared frame bits).  dev_buf: caller-owned,
+ * 256-byte aligned, stn_checkpoint_bytes long.  Both synchronise. */
+size_t stn_checkpoint_bytes(const stn_ctx *ctx);
+stn_status stn_checkpoint_save(stn_ctx *ctx, void *dev_buf);
+stn_status stn_checkpoint_load(stn_ctx *ctx, const void *dev_buf);
+
 /* Kernel classes for stn_profile / stn_profile_read. */
 enum { STN_K_TABLEAU = 0,  /* tableau gates, rewrite, frame change */
        STN_K_BUILD = 1,    /* bond-2 operator blocks, copies, coefficients */

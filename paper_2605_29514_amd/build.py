@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstn.so")
-SOURCES = ["api.hip", "tableau.hip", "mps.hip", "layer.hip"]
+SOURCES = ["api.hip", "tableau.hip", "mps.hip", "layer.hip", "adjoint.hip"]
 ARCH = "gfx950"
 
 

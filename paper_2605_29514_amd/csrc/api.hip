@@ -155,6 +155,19 @@ struct stn_ctx {
   Prof prof;
   double prof_ms[K_COUNT] = {};
   long long prof_launches[K_COUNT] = {};
+  // gradient tape: one record per non-Clifford step, each holding the
+  // pre-step state and the per-shot data of the step; one more snapshot
+  // after the last step
+  struct TapeStep { int kind, l, r, pivot, rot; };   // kind 0 rotation, 1 measurement
+  bool taping = false, tape_closed = false;
+  char *tape = nullptr;
+  int tape_max = 0;
+  std::vector<TapeStep> steps;
+  int tape_rot = 0;
+  // adjoint state
+  MpsDev adj{};
+  bool adj_ready = false;
+  int adj_center = 0;
   ~stn_ctx() {
     for (auto e : prof.pool) hipEventDestroy(e);
   }
@@ -185,6 +198,81 @@ int dmax_h(int n, int chi, int b) {
   return (int)(phys < chi ? phys : chi);
 }
 
+// Lays out one batch of MPS (slots, workspace slots for bonds up to wmul x
+// the cap, bonds, per-shot scratch) in L; fills m when base != nullptr and
+// returns the host copy of the slot offset tables (site_off, site_cap,
+// ws_off, ws_cap) in offs, which the caller uploads.
+void plan_mps(Layout &L, int n, int S, int chi, size_t esz, int wmul, char *base, MpsDev *mp,
+              std::vector<int64_t> *offs) {
+  std::vector<int64_t> site_off(n), site_cap(n), ws_off(n), ws_cap(n);
+  int64_t so = 0, wo = 0, Tcap = 1;
+  for (int j = 0; j < n; ++j) {
+    int64_t dl = dmax_h(n, chi, j), dr = dmax_h(n, chi, j + 1);
+    site_cap[j] = dl * 2 * dr;
+    site_off[j] = so;
+    so += site_cap[j] * S;
+    ws_cap[j] = (wmul * dl) * 2 * (wmul * dr);
+    ws_off[j] = wo;
+    wo += ws_cap[j] * S;
+    Tcap = std::max<int64_t>(Tcap, ws_cap[j]);
+  }
+  int64_t chi_eff = 1;
+  for (int b = 0; b <= n; ++b) chi_eff = std::max<int64_t>(chi_eff, dmax_h(n, chi, b));
+  const int64_t nn = 2 * chi_eff;
+  size_t o_soff = L.off((size_t)n * 8), o_scap = L.off((size_t)n * 8), o_woff = L.off((size_t)n * 8),
+         o_wcap = L.off((size_t)n * 8);
+  size_t o_bond = L.off((size_t)S * (n + 1) * 4), o_wb = L.off((size_t)S * (n + 1) * 4),
+         o_aux = L.off((size_t)S * 8 * 4);
+  size_t o_logp = L.off((size_t)S * 8), o_fid = L.off((size_t)S * 8), o_p0 = L.off((size_t)S * 8),
+         o_nrm = L.off((size_t)S * 8), o_pm = L.off((size_t)S * 8), o_tr = L.off((size_t)S * 4),
+         o_coef = L.off((size_t)S * 2 * sizeof(c64));
+  size_t o_mps = L.off((size_t)so * esz), o_ws = L.off((size_t)wo * esz);
+  size_t o_T = L.off((size_t)Tcap * S * esz), o_R = L.off((size_t)Tcap * S * esz);
+  size_t o_N = L.off((size_t)wmul * chi_eff * chi_eff * S * esz), o_Vt = L.off((size_t)nn * chi_eff * S * esz);
+  size_t o_G = L.off((size_t)nn * nn * S * sizeof(c64)), o_V = L.off((size_t)nn * nn * S * sizeof(c64));
+  size_t o_ev = L.off((size_t)nn * S * 8);
+  size_t o_E = L.off((size_t)chi_eff * chi_eff * S * sizeof(c64)),
+         o_F = L.off((size_t)chi_eff * 2 * chi_eff * S * sizeof(c64));
+  const int64_t Jcap = (int64_t)align_up(layer_fallback_bytes((int)chi_eff));
+  size_t o_J = L.off((size_t)Jcap * S);
+  if (base) {
+    MpsDev &m = *mp;
+    m.n = n; m.S = S; m.chi = chi;
+    m.site_off = (int64_t *)(base + o_soff); m.site_cap = (int64_t *)(base + o_scap);
+    m.ws_off = (int64_t *)(base + o_woff); m.ws_cap = (int64_t *)(base + o_wcap);
+    m.mps = base + o_mps; m.ws = base + o_ws;
+    m.bond = (int *)(base + o_bond); m.wb = (int *)(base + o_wb); m.aux = (int *)(base + o_aux);
+    m.T = base + o_T; m.T_cap = Tcap;
+    m.R = base + o_R; m.R_cap = Tcap;
+    m.N = base + o_N; m.N_cap = wmul * chi_eff * chi_eff;
+    m.Vt = base + o_Vt; m.Vt_cap = nn * chi_eff;
+    m.G = (c64 *)(base + o_G); m.G_cap = nn * nn;
+    m.V = (c64 *)(base + o_V); m.V_cap = nn * nn;
+    m.ev = (double *)(base + o_ev); m.ev_cap = nn;
+    m.E = (c64 *)(base + o_E); m.E_cap = chi_eff * chi_eff;
+    m.F = (c64 *)(base + o_F); m.F_cap = chi_eff * 2 * chi_eff;
+    m.J = base + o_J; m.J_cap = Jcap;
+    m.logp = (double *)(base + o_logp); m.fid = (double *)(base + o_fid);
+    m.p0 = (double *)(base + o_p0); m.nrm = (double *)(base + o_nrm);
+    m.pm = (double *)(base + o_pm); m.trunc = (int *)(base + o_tr);
+    m.coef = (c64 *)(base + o_coef);
+    m.wmul = wmul;
+    m.keep_norm = 0;
+    m.prof = 0;
+  }
+  if (offs) {
+    offs->clear();
+    for (auto *v : {&site_off, &site_cap, &ws_off, &ws_cap}) offs->insert(offs->end(), v->begin(), v->end());
+  }
+}
+
+// Bytes of the MPS slots of one batch (the part a state snapshot copies).
+size_t mps_slot_bytes(int n, int S, int chi, size_t esz) {
+  size_t so = 0;
+  for (int j = 0; j < n; ++j) so += (size_t)dmax_h(n, chi, j) * 2 * dmax_h(n, chi, j + 1) * S;
+  return so * esz;
+}
+
 // Computes the workspace layout; when base != nullptr also fills ctx pointers.
 size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> *offs) {
   const int n = c.n_qubits, S = c.n_shots, chi = c.chi_max;
@@ -200,37 +288,8 @@ size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> 
   size_t o_ops = L.off((size_t)n * 8 * sizeof(c64)), o_eops = L.off((size_t)n * 4 * sizeof(c64));
   size_t o_err = L.off(4);
   size_t o_work = L.off((size_t)(2 * K_COUNT + 2) * 8);
-  // MPS slots
-  std::vector<int64_t> site_off(n), site_cap(n), ws_off(n), ws_cap(n);
-  int64_t so = 0, wo = 0, Tcap = 1;
-  for (int j = 0; j < n; ++j) {
-    int64_t dl = dmax_h(n, chi, j), dr = dmax_h(n, chi, j + 1);
-    site_cap[j] = dl * 2 * dr;
-    site_off[j] = so;
-    so += site_cap[j] * S;
-    ws_cap[j] = (2 * dl) * 2 * (2 * dr);
-    ws_off[j] = wo;
-    wo += ws_cap[j] * S;
-    Tcap = std::max<int64_t>(Tcap, ws_cap[j]);
-  }
-  int64_t chi_eff = 1;
-  for (int b = 0; b <= n; ++b) chi_eff = std::max<int64_t>(chi_eff, dmax_h(n, chi, b));
-  const int64_t nn = 2 * chi_eff;
-  size_t o_soff = L.off((size_t)n * 8), o_scap = L.off((size_t)n * 8), o_woff = L.off((size_t)n * 8),
-         o_wcap = L.off((size_t)n * 8);
-  size_t o_bond = L.off((size_t)S * (n + 1) * 4), o_wb = L.off((size_t)S * (n + 1) * 4),
-         o_aux = L.off((size_t)S * 8 * 4);
-  size_t o_logp = L.off((size_t)S * 8), o_fid = L.off((size_t)S * 8), o_p0 = L.off((size_t)S * 8),
-         o_nrm = L.off((size_t)S * 8), o_coef = L.off((size_t)S * 2 * sizeof(c64));
-  size_t o_mps = L.off((size_t)so * esz), o_ws = L.off((size_t)wo * esz);
-  size_t o_T = L.off((size_t)Tcap * S * esz), o_R = L.off((size_t)Tcap * S * esz);
-  size_t o_N = L.off((size_t)nn * chi_eff * S * esz), o_Vt = L.off((size_t)nn * chi_eff * S * esz);
-  size_t o_G = L.off((size_t)nn * nn * S * sizeof(c64)), o_V = L.off((size_t)nn * nn * S * sizeof(c64));
-  size_t o_ev = L.off((size_t)nn * S * 8);
-  size_t o_E = L.off((size_t)chi_eff * chi_eff * S * sizeof(c64)),
-         o_F = L.off((size_t)chi_eff * 2 * chi_eff * S * sizeof(c64));
-  const int64_t Jcap = (int64_t)align_up(layer_fallback_bytes((int)chi_eff));
-  size_t o_J = L.off((size_t)Jcap * S);
+  MpsDev *mp = ctx && base ? &ctx->mps : nullptr;
+  plan_mps(L, n, S, chi, esz, 2, base && ctx ? base : nullptr, mp, offs);
   if (ctx && base) {
     ctx->n = n; ctx->S = S; ctx->chi = chi; ctx->prec = c.precision; ctx->W = W; ctx->SW = SW;
     ctx->esz = esz;
@@ -245,32 +304,9 @@ size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> 
     ctx->d_eops = (c64 *)(base + o_eops);
     ctx->d_err = (int *)(base + o_err);
     MpsDev &m = ctx->mps;
-    m.n = n; m.S = S; m.chi = chi;
-    m.site_off = (int64_t *)(base + o_soff); m.site_cap = (int64_t *)(base + o_scap);
-    m.ws_off = (int64_t *)(base + o_woff); m.ws_cap = (int64_t *)(base + o_wcap);
-    m.mps = base + o_mps; m.ws = base + o_ws;
-    m.bond = (int *)(base + o_bond); m.wb = (int *)(base + o_wb); m.aux = (int *)(base + o_aux);
-    m.T = base + o_T; m.T_cap = Tcap;
-    m.R = base + o_R; m.R_cap = Tcap;
-    m.N = base + o_N; m.N_cap = nn * chi_eff;
-    m.Vt = base + o_Vt; m.Vt_cap = nn * chi_eff;
-    m.G = (c64 *)(base + o_G); m.G_cap = nn * nn;
-    m.V = (c64 *)(base + o_V); m.V_cap = nn * nn;
-    m.ev = (double *)(base + o_ev); m.ev_cap = nn;
-    m.E = (c64 *)(base + o_E); m.E_cap = chi_eff * chi_eff;
-    m.F = (c64 *)(base + o_F); m.F_cap = chi_eff * 2 * chi_eff;
-    m.J = base + o_J; m.J_cap = Jcap;
-    m.logp = (double *)(base + o_logp); m.fid = (double *)(base + o_fid);
-    m.p0 = (double *)(base + o_p0); m.nrm = (double *)(base + o_nrm);
-    m.coef = (c64 *)(base + o_coef);
     m.err = ctx->d_err;
     m.eps_cut = c.eps_cut;
-    m.prof = 0;
     m.work = (double *)(base + o_work);
-    if (offs) {
-      offs->clear();
-      for (auto *v : {&site_off, &site_cap, &ws_off, &ws_cap}) offs->insert(offs->end(), v->begin(), v->end());
-    }
   }
   return L.total;
 }
@@ -404,6 +440,74 @@ void two_term(stn_ctx *c, int l, int r, bool unitary) {
   c->center = l;
 }
 
+// ------------------------------------------------------ gradient tape
+// Per-step record: pre-step state snapshot (MPS slots, bonds), the Pauli
+// bits and signs of P', the outcome mask, and per shot the angle, the
+// truncation flag, the squared norm before renormalisation and the outcome
+// probability.
+struct RecLayout {
+  size_t snap_mps, snap_bond, bits, sign, mmask, theta, trunc, nrm, pm, total;
+};
+RecLayout rec_layout(const stn_ctx *c) {
+  Layout L;
+  RecLayout r;
+  r.snap_mps = L.off(mps_slot_bytes(c->n, c->S, c->chi, c->esz));
+  r.snap_bond = L.off((size_t)c->S * (c->n + 1) * 4);
+  r.bits = L.off((size_t)2 * c->W * 8);
+  r.sign = L.off((size_t)c->SW * 8);
+  r.mmask = L.off((size_t)c->SW * 8);
+  r.theta = L.off((size_t)c->S * 8);
+  r.trunc = L.off((size_t)c->S * 4);
+  r.nrm = L.off((size_t)c->S * 8);
+  r.pm = L.off((size_t)c->S * 8);
+  r.total = L.total;
+  return r;
+}
+
+MpsDev snapshot_view(const stn_ctx *c, char *rec) {
+  const RecLayout R = rec_layout(c);
+  MpsDev v = c->mps;
+  v.mps = rec + R.snap_mps;
+  v.bond = (int *)(rec + R.snap_bond);
+  return v;
+}
+
+hipError_t take_snapshot(stn_ctx *c, char *rec) {
+  const RecLayout R = rec_layout(c);
+  hipError_t e = hipMemcpyAsync(rec + R.snap_mps, c->mps.mps, mps_slot_bytes(c->n, c->S, c->chi, c->esz),
+                                hipMemcpyDeviceToDevice, c->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rec + R.snap_bond, c->mps.bond, (size_t)c->S * (c->n + 1) * 4, hipMemcpyDeviceToDevice, c->st);
+  return e;
+}
+
+// Before a recorded step: snapshot, Pauli data, per-shot flags reset.
+stn_status tape_pre(stn_ctx *c, char **rec, const uint64_t *d_bits, const uint64_t *d_sign) {
+  if ((int)c->steps.size() >= c->tape_max) return fail(c, STN_ENOMEM, "gradient tape is full");
+  const RecLayout R = rec_layout(c);
+  char *r = c->tape + c->steps.size() * R.total;
+  hipError_t e = take_snapshot(c, r);
+  if (e == hipSuccess) e = hipMemcpyAsync(r + R.bits, d_bits, (size_t)2 * c->W * 8, hipMemcpyDeviceToDevice, c->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(r + R.sign, d_sign, (size_t)c->SW * 8, hipMemcpyDeviceToDevice, c->st);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  launch_step_reset(c->mps, c->st);
+  *rec = r;
+  return STN_OK;
+}
+
+stn_status tape_post(stn_ctx *c, char *r, int kind, int l, int rr, int pivot) {
+  const RecLayout R = rec_layout(c);
+  hipError_t e = hipMemcpyAsync(r + R.trunc, c->mps.trunc, (size_t)c->S * 4, hipMemcpyDeviceToDevice, c->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(r + R.nrm, c->mps.nrm, (size_t)c->S * 8, hipMemcpyDeviceToDevice, c->st);
+  if (e == hipSuccess && kind == 1) {
+    e = hipMemcpyAsync(r + R.pm, c->mps.pm, (size_t)c->S * 8, hipMemcpyDeviceToDevice, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(r + R.mmask, c->d_mmask, (size_t)c->SW * 8, hipMemcpyDeviceToDevice, c->st);
+  }
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  c->steps.push_back({kind, l, rr, pivot, kind == 0 ? c->tape_rot++ : -1});
+  return STN_OK;
+}
+
 template <typename T>
 stn_status rotate_impl(stn_ctx *c, const int32_t *qs, int n_rot, const double *theta, int64_t stride) {
   for (int r0 = 0; r0 < n_rot; r0 += kRotChunk) {
@@ -420,7 +524,7 @@ stn_status rotate_impl(stn_ctx *c, const int32_t *qs, int n_rot, const double *t
       b.p[i] = p;
     }
     launch_tab_products(c->tab, b, c->d_pbits, c->d_psgn, c->d_err, c->st);
-    const bool fused = c->layer_mode == 2 || (c->layer_mode == 0 && c->S >= 64);
+    const bool fused = !c->taping && (c->layer_mode == 2 || (c->layer_mode == 0 && c->S >= 64));
     if (fused) {
       RotLayer L{};
       L.n_rot = cnt;
@@ -446,10 +550,20 @@ stn_status rotate_impl(stn_ctx *c, const int32_t *qs, int n_rot, const double *t
       span_of(c, px.data(), pz.data(), &l, &r, &piv);
       if (l < 0) return fail(c, STN_EINVAL, "rotation Pauli is the identity");
       const uint64_t *bits = c->d_pbits + (size_t)i * 2 * c->W;
+      char *rec = nullptr;
+      if (c->taping) {
+        stn_status ts = tape_pre(c, &rec, bits, c->d_psgn + (size_t)i * c->SW);
+        if (ts != STN_OK) return ts;
+        launch_gather_theta(theta, stride, r0 + i, (double *)(rec + rec_layout(c).theta), c->S, c->st);
+      }
       launch_ops_rotation(bits, c->W, l, r, c->d_ops, c->st);
       launch_coef_rotation(c->d_psgn + (size_t)i * c->SW, c->S, theta, stride, r0 + i, c->mps.coef,
                            c->d_err, c->st);
       two_term<T>(c, l, r, true);
+      if (c->taping) {
+        stn_status ts = tape_post(c, rec, 0, l, r, -1);
+        if (ts != STN_OK) return ts;
+      }
     }
   }
   return check_launch(c);
@@ -466,12 +580,21 @@ stn_status measure_impl(stn_ctx *c, const int32_t *qs, int n_meas, int reset, co
     int l, r, piv;
     span_of(c, px.data(), pz.data(), &l, &r, &piv);
     launch_tab_snapshot(c->tab, row, c->d_snap, c->st);
+    char *rec = nullptr;
+    if (c->taping) {
+      stn_status ts = tape_pre(c, &rec, c->d_snap, c->d_snap + 2 * c->W);
+      if (ts != STN_OK) return ts;
+    }
     launch_ops_measure(c->d_snap, c->W, l, r, piv, c->d_ops, c->d_eops, c->st);
     move_center_into<T>(c, l, l);
     mps_expect<T>(c->mps, l, r, c->d_eops, c->st);
     launch_outcome(c->mps, c->d_snap + 2 * c->W, piv, r + 1, u, forced, n_meas, i, out, prob,
                    c->d_negmask, c->d_mmask, c->st);
     two_term<T>(c, l, r, false);
+    if (c->taping) {
+      stn_status ts = tape_post(c, rec, 1, l, r, piv);
+      if (ts != STN_OK) return ts;
+    }
     if (piv >= 0) {
       launch_tab_frame(c->tab, c->d_snap, c->d_negmask, c->d_tables, c->st);
       shadow_frame(c, px.data(), pz.data(), piv);
@@ -479,6 +602,98 @@ stn_status measure_impl(stn_ctx *c, const int32_t *qs, int n_meas, int reset, co
     if (reset) launch_tab_flip(c->tab, row, c->d_mmask, c->st);
   }
   return check_launch(c);
+}
+
+// ------------------------------------------------------ adjoint pass
+template <typename T>
+void adj_move_into(stn_ctx *c, int l, int r) {
+  while (c->adj_center < l) { mps_move_right<T>(c->adj, c->adj_center, c->st); c->adj_center++; }
+  while (c->adj_center > r) { mps_move_left<T>(c->adj, c->adj_center, c->st); c->adj_center--; }
+}
+
+// mu <- a O1 mu + b O2 mu over [l, r] (ops and coefficients on the device),
+// compressed with its norm kept.
+template <typename T>
+void adj_two_term(stn_ctx *c, int l, int r) {
+  MpsDev &mu = c->adj;
+  adj_move_into<T>(c, l, r);
+  if (l == r) {
+    adj_move_into<T>(c, l, l);
+    mps_apply_single<T>(mu, l, c->d_ops, c->st);
+    return;
+  }
+  mps_build<T>(mu, l, r, c->d_ops, c->st);
+  mps_sweep_lr<T>(mu, l, r, c->st);
+  mps_sweep_rl<T>(mu, l, r, c->st);
+  c->adj_center = l;
+}
+
+template <typename T>
+stn_status backward_impl(stn_ctx *c, double *grad, int64_t stride) {
+  const RecLayout R = rec_layout(c);
+  const int K = (int)c->steps.size(), S = c->S, n = c->n;
+  std::vector<int> tr((size_t)K * S);
+  hipError_t e = hipStreamSynchronize(c->st);
+  for (int k = 0; k < K && e == hipSuccess; ++k)
+    e = hipMemcpy(&tr[(size_t)k * S], c->tape + k * R.total + R.trunc, (size_t)S * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  MpsDev &mu = c->adj;
+  for (int k = K - 1; k >= 0; --k) {
+    const auto &stp = c->steps[k];
+    char *rec = c->tape + k * R.total, *nxt = c->tape + (k + 1) * R.total;
+    const MpsDev ph = snapshot_view(c, rec), pa = snapshot_view(c, nxt);
+    const uint64_t *bits = (const uint64_t *)(rec + R.bits), *sign = (const uint64_t *)(rec + R.sign);
+    const uint64_t *mmask = (const uint64_t *)(rec + R.mmask);
+    const double *nrm = (const double *)(rec + R.nrm), *pm = (const double *)(rec + R.pm);
+    const int l = stp.l, r = stp.r;
+    bool any = false;
+    for (int s = 0; s < S; ++s) any = any || tr[(size_t)k * S + s];
+    if (any && l < r) {                                 // frozen projection of the step
+      adj_move_into<T>(c, l, l);
+      mps_project_right<T>(mu, pa, l, (const int *)(rec + R.trunc), c->st);
+    }
+    if (stp.kind == 0) {                                // mu <- R^dag mu / n
+      launch_ops_rotation(bits, c->W, l, r, c->d_ops, c->st);
+      launch_adj_coef(mu, 0, -1, (const double *)(rec + R.theta), sign, nullptr, nrm, nullptr, c->st);
+    } else {                                            // mu <- M^dag mu / n
+      if (stp.pivot < 0) launch_ops_measure(bits, c->W, l, r, -1, c->d_ops, c->d_eops, c->st);
+      else launch_ops_measure_adj(bits, c->W, l, r, stp.pivot, c->d_ops, c->st);
+      launch_adj_coef(mu, 1, stp.pivot, nullptr, sign, mmask, nrm, nullptr, c->st);
+    }
+    adj_two_term<T>(c, l, r);
+    if (stp.kind == 0) {                                // dJ/dtheta = 2 sigma Im <mu|P'|phi>
+      launch_ops_measure(bits, c->W, l, r, -1, c->d_ops, c->d_eops, c->st);
+      mps_overlap_grad<T>(mu, ph, c->d_eops, l, r, sign, grad + stp.rot, stride, c->st);
+    } else {                                            // mu <- mu + A phi / p - phi
+      launch_ops_rotation(bits, c->W, l, r, c->d_ops, c->st);
+      launch_adj_coef(mu, 2, stp.pivot, nullptr, sign, mmask, nrm, pm, c->st);
+      mps_build_sum<T>(mu, ph, l, r, c->d_ops, c->st);
+      mps_sweep_lr<T>(mu, 0, n - 1, c->st);
+      mps_sweep_rl<T>(mu, 0, n - 1, c->st);
+      c->adj_center = 0;
+    }
+  }
+  return check_launch(c);
+}
+
+// Checkpoint of the forward state: MPS slots, bonds, tableau, log P and
+// fidelity, and the host shadow of the shared bits with the centre.
+struct CkLayout { size_t mps, bond, x, z, s, logp, fid, hx, hz, center, total; };
+CkLayout ck_layout(const stn_ctx *c) {
+  Layout L;
+  CkLayout k;
+  k.mps = L.off(mps_slot_bytes(c->n, c->S, c->chi, c->esz));
+  k.bond = L.off((size_t)c->S * (c->n + 1) * 4);
+  k.x = L.off((size_t)2 * c->n * c->W * 8);
+  k.z = L.off((size_t)2 * c->n * c->W * 8);
+  k.s = L.off((size_t)2 * c->n * c->SW * 8);
+  k.logp = L.off((size_t)c->S * 8);
+  k.fid = L.off((size_t)c->S * 8);
+  k.hx = L.off((size_t)2 * c->n * c->W * 8);
+  k.hz = L.off((size_t)2 * c->n * c->W * 8);
+  k.center = L.off(8);
+  k.total = L.total;
+  return k;
 }
 
 }  // namespace
@@ -780,6 +995,132 @@ stn_status stn_set_layer_threads(stn_ctx *c, int threads) {
 stn_status stn_set_center(stn_ctx *c, int center) {
   if (!c || center < 0 || center >= c->n) return STN_EINVAL;
   c->center = center;
+  return STN_OK;
+}
+
+// ------------------------------------------------------------ gradients
+size_t stn_tape_bytes(const stn_ctx *c, int max_steps) {
+  if (!c || max_steps < 1) return 0;
+  return (size_t)(max_steps + 1) * rec_layout(c).total;
+}
+
+stn_status stn_tape_begin(stn_ctx *c, void *dev_tape, size_t bytes, int max_steps) {
+  if (!c || !dev_tape || max_steps < 1 || ((uintptr_t)dev_tape & 255)) return STN_EINVAL;
+  if (bytes < stn_tape_bytes(c, max_steps)) return fail(c, STN_ENOMEM, "tape buffer too small");
+  c->tape = (char *)dev_tape;
+  c->tape_max = max_steps;
+  c->steps.clear();
+  c->tape_rot = 0;
+  c->taping = true;
+  c->tape_closed = false;
+  return STN_OK;
+}
+
+stn_status stn_tape_end(stn_ctx *c, int *n_rotations) {
+  if (!c || !c->taping) return STN_ESTATE;
+  const RecLayout R = rec_layout(c);
+  hipError_t e = take_snapshot(c, c->tape + c->steps.size() * R.total);
+  c->taping = false;
+  c->tape_closed = true;
+  if (n_rotations) *n_rotations = c->tape_rot;
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  return check_launch(c);
+}
+
+size_t stn_adjoint_bytes(const stn_ctx *c, int chi_adj) {
+  if (!c || chi_adj < 1 || chi_adj > 512) return 0;
+  Layout L;
+  plan_mps(L, c->n, c->S, chi_adj, c->esz, 3, nullptr, nullptr, nullptr);
+  return L.total;
+}
+
+stn_status stn_adjoint_init(stn_ctx *c, void *dev_buf, size_t bytes, int chi_adj) {
+  if (!c || !dev_buf || ((uintptr_t)dev_buf & 255)) return STN_EINVAL;
+  const size_t need = stn_adjoint_bytes(c, chi_adj);
+  if (need == 0) return STN_EINVAL;
+  if (bytes < need) return fail(c, STN_ENOMEM, "adjoint buffer too small");
+  Layout L;
+  std::vector<int64_t> offs;
+  plan_mps(L, c->n, c->S, chi_adj, c->esz, 3, (char *)dev_buf, &c->adj, &offs);
+  MpsDev &mu = c->adj;
+  mu.err = c->d_err;
+  mu.eps_cut = c->cfg.eps_cut;
+  mu.work = c->mps.work;
+  mu.keep_norm = 1;
+  hipError_t e = hipSuccess;
+  int64_t *dst[4] = {mu.site_off, mu.site_cap, mu.ws_off, mu.ws_cap};
+  for (int a = 0; a < 4; ++a)
+    e = e ? e : hipMemcpyAsync(dst[a], offs.data() + (size_t)a * c->n, (size_t)c->n * 8, hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  const int rows = std::max(4 * c->chi, 6 * chi_adj);     // QR rows of doubled / summed tensors
+  if (e == hipSuccess) e = c->prec == STN_FP64 ? mps_prepare<double>(rows) : mps_prepare<float>(rows);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  c->adj_ready = true;
+  return stn_adjoint_zero(c);
+}
+
+stn_status stn_adjoint_zero(stn_ctx *c) {
+  if (!c || !c->adj_ready) return STN_ESTATE;
+  if (c->prec == STN_FP64) mps_zero<double>(c->adj, c->st);
+  else mps_zero<float>(c->adj, c->st);
+  c->adj_center = 0;
+  return check_launch(c);
+}
+
+stn_status stn_backward(stn_ctx *c, double *dev_grad, int64_t grad_stride) {
+  if (!c || !dev_grad || grad_stride < 0) return STN_EINVAL;
+  if (!c->adj_ready || !c->tape_closed) return fail(c, STN_ESTATE, "backward needs a closed tape and an adjoint state");
+  if (grad_stride < c->tape_rot && c->S > 1) return STN_EINVAL;
+  ProfScope ps(c);
+  stn_status st = c->prec == STN_FP64 ? backward_impl<double>(c, dev_grad, grad_stride)
+                                      : backward_impl<float>(c, dev_grad, grad_stride);
+  if (st != STN_OK) return st;
+  return sync_status(c);
+}
+
+size_t stn_checkpoint_bytes(const stn_ctx *c) { return c ? ck_layout(c).total : 0; }
+
+stn_status stn_checkpoint_save(stn_ctx *c, void *dev_buf) {
+  if (!c || !dev_buf || ((uintptr_t)dev_buf & 255)) return STN_EINVAL;
+  const CkLayout K = ck_layout(c);
+  char *b = (char *)dev_buf;
+  const size_t tb = (size_t)2 * c->n * c->W * 8;
+  int64_t center = c->center;
+  hipError_t e = hipMemcpyAsync(b + K.mps, c->mps.mps, mps_slot_bytes(c->n, c->S, c->chi, c->esz), hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(b + K.bond, c->mps.bond, (size_t)c->S * (c->n + 1) * 4, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(b + K.x, c->tab.x, tb, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(b + K.z, c->tab.z, tb, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(b + K.s, c->tab.s, (size_t)2 * c->n * c->SW * 8, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(b + K.logp, c->mps.logp, (size_t)c->S * 8, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(b + K.fid, c->mps.fid, (size_t)c->S * 8, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipStreamSynchronize(c->st);
+  e = e ? e : hipMemcpy(b + K.hx, c->hx.data(), tb, hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(b + K.hz, c->hz.data(), tb, hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(b + K.center, &center, 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  return STN_OK;
+}
+
+stn_status stn_checkpoint_load(stn_ctx *c, const void *dev_buf) {
+  if (!c || !dev_buf || ((uintptr_t)dev_buf & 255)) return STN_EINVAL;
+  const CkLayout K = ck_layout(c);
+  const char *b = (const char *)dev_buf;
+  const size_t tb = (size_t)2 * c->n * c->W * 8;
+  int64_t center = 0;
+  hipError_t e = hipStreamSynchronize(c->st);
+  e = e ? e : hipMemcpy(c->hx.data(), b + K.hx, tb, hipMemcpyDeviceToHost);
+  e = e ? e : hipMemcpy(c->hz.data(), b + K.hz, tb, hipMemcpyDeviceToHost);
+  e = e ? e : hipMemcpy(&center, b + K.center, 8, hipMemcpyDeviceToHost);
+  e = e ? e : hipMemcpyAsync(c->mps.mps, b + K.mps, mps_slot_bytes(c->n, c->S, c->chi, c->esz), hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(c->mps.bond, b + K.bond, (size_t)c->S * (c->n + 1) * 4, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(c->tab.x, b + K.x, tb, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(c->tab.z, b + K.z, tb, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(c->tab.s, b + K.s, (size_t)2 * c->n * c->SW * 8, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(c->mps.logp, b + K.logp, (size_t)c->S * 8, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipMemcpyAsync(c->mps.fid, b + K.fid, (size_t)c->S * 8, hipMemcpyDeviceToDevice, c->st);
+  e = e ? e : hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+  c->center = (int)center;
   return STN_OK;
 }
 

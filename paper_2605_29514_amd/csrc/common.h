@@ -124,9 +124,13 @@ struct MpsDev {
   c64 *F;    int64_t F_cap;
   void *J;   int64_t J_cap;     // bytes: fused-kernel fallbacks (reflectors, Jacobi pairs)
   double *logp, *fid, *p0, *nrm;  // [S]
+  double *pm;                   // [S] probability of the last recorded outcome
+  int *trunc;                   // [S] set when chi_max dropped weight above the cut
   c64 *coef;                    // [S][2]  (a, b)
   int *err;
   double eps_cut;
+  int wmul;                     // workspace bond multiplier (2: two-term steps, 3: sums)
+  int keep_norm;                // 1: compression leaves the norm (adjoint state)
   int prof;                     // count algorithmic work when nonzero
   double *work;                 // [K_COUNT][2]: flops, bytes
 };
@@ -154,6 +158,23 @@ template <typename T> void mps_apply_single(const MpsDev &m, int site, const c64
 template <typename T> void mps_build(const MpsDev &m, int l, int r, const c64 *d_ops, hipStream_t st);
 template <typename T> void mps_sweep_lr(const MpsDev &m, int l, int r, hipStream_t st);
 template <typename T> void mps_sweep_rl(const MpsDev &m, int l, int r, hipStream_t st);
+// ------------------------------------------------------------- adjoint
+// ph: the forward state (a snapshot view), mu: the adjoint state.
+void launch_step_reset(const MpsDev &m, hipStream_t st);
+void launch_gather_theta(const double *d_theta, int64_t stride, int idx, double *d_dst, int S, hipStream_t st);
+void launch_ops_measure_adj(const uint64_t *d_bits, int W, int l, int r, int pivot, c64 *d_ops, hipStream_t st);
+// coefficients of the adjoint maps per shot (kind 0: rotation R^dag / n,
+// 1: measurement M^dag / n, 2: the term (1/2p - 1) phi + (s sigma / 2p) P' phi)
+void launch_adj_coef(const MpsDev &mu, int kind, int pivot, const double *d_theta, const uint64_t *d_sign,
+                     const uint64_t *d_mmask, const double *d_nrm, const double *d_pm, hipStream_t st);
+template <typename T> void mps_build_sum(const MpsDev &mu, const MpsDev &ph, int l, int r, const c64 *d_ops,
+                                         hipStream_t st);
+template <typename T> void mps_project_right(const MpsDev &mu, const MpsDev &ph, int l, const int *d_flag,
+                                             hipStream_t st);
+template <typename T> void mps_overlap_grad(const MpsDev &mu, const MpsDev &ph, const c64 *d_eops, int l,
+                                            int r, const uint64_t *d_sign, double *d_grad, int64_t stride,
+                                            hipStream_t st);
+template <typename T> void mps_zero(const MpsDev &m, hipStream_t st);
 template <typename T> void mps_move_right(const MpsDev &m, int c, hipStream_t st);
 template <typename T> void mps_move_left(const MpsDev &m, int c, hipStream_t st);
 template <typename T> void mps_normalize_site(const MpsDev &m, int site, hipStream_t st);

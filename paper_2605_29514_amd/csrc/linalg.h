@@ -407,6 +407,7 @@ __device__ int select_body(const MpsDev &m, int s, int j, cplx<T> *Vt) {
     const int e = j < m.n - j ? j : m.n - j;           // physical bound 2^min(j, n-j)
     if (e < 30 && k > (1 << e)) k = 1 << e;
     if (k < 1) k = 1;
+    if (k < cnt) m.trunc[s] = 1;                       // weight above the cut was dropped
     double disc = 0;
     for (int i = k; i < nn; ++i) disc += fmax(ev[i], 0.0);
     const double wgt = tot > 0 ? disc / tot : 0.0;
@@ -443,12 +444,12 @@ __device__ void finish_body(const MpsDev &m, int s, int l, const cplx<T> *X) {
   double part = 0;
   for (int e = threadIdx.x; e < cnt; e += NT) part += norm2(cvt<double>(X[e]));
   const double n2 = bsum<NT>(part);
-  if (!(n2 > 0) || isinf(n2)) {
+  if (m.keep_norm ? (isinf(n2) || !(n2 == n2)) : (!(n2 > 0) || isinf(n2))) {
     if (threadIdx.x == 0) atomicOr(m.err, STN_ERR_NUMERIC);
     __syncthreads();
     return;
   }
-  const double inv = 1.0 / sqrt(n2);
+  const double inv = m.keep_norm ? 1.0 : 1.0 / sqrt(n2);
   cplx<T> *out = slot<T>(m, l, s);
   for (int e = threadIdx.x; e < cnt; e += NT) out[e] = cvt<T>(inv * cvt<double>(X[e]));
   if (threadIdx.x == 0) {

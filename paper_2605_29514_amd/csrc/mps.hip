@@ -266,6 +266,7 @@ __global__ void k_normalize(MpsDev m, int site) {
     if (threadIdx.x == 0) atomicOr(m.err, STN_ERR_NUMERIC);
     return;
   }
+  if (threadIdx.x == 0) m.nrm[s] = n2;
   double inv = 1.0 / sqrt(n2);
   for (int e = threadIdx.x; e < cnt; e += TB) A[e] = cvt<T>(inv * cvt<double>(A[e]));
 }
@@ -472,6 +473,7 @@ __global__ void k_outcome(MpsDev m, const uint64_t *snap_sign, int pivot, int dr
     double pm = mm ? 1.0 - p0 : p0;
     if (pm <= 0) { atomicOr(m.err, STN_ERR_ZEROPROB); pm = 1e-300; }
     m.logp[s] += log(pm);
+    m.pm[s] = pm;
     if (out) out[(size_t)s * n_meas + mi] = (uint8_t)mm;
     if (prob) prob[(size_t)s * n_meas + mi] = pm;
     m.p0[s] = p0;
@@ -531,12 +533,13 @@ static size_t qr_lds(int rows) {
 }
 
 template <typename T> void mps_sweep_lr(const MpsDev &m, int l, int r, hipStream_t st) {
+  const int wm = m.wmul;                // largest multiple of a bond in the workspace
   for (int j = l; j < r; ++j) {
-    int rows = 2 * (j == l ? dmax(m, j, 1) : 2 * dmax(m, j, 1));
-    int cols = 2 * dmax(m, j + 1, 1);
+    int rows = 2 * (j == l ? dmax(m, j, 1) : wm * dmax(m, j, 1));
+    int cols = wm * dmax(m, j + 1, 1);
     KLAUNCH(K_QR, k_qr_lr<T>, dim3(m.S), dim3(TB), qr_lds(rows), st, m, j, rows);
     int p = imin(rows, cols);
-    int ncol = 2 * (j + 1 == r ? dmax(m, j + 2, 1) : 2 * dmax(m, j + 2, 1));
+    int ncol = 2 * (j + 1 == r ? dmax(m, j + 2, 1) : wm * dmax(m, j + 2, 1));
     KLAUNCH(K_GEMM, k_absorb_lr<T>, gemm_grid(p, ncol, m.S), dim3(TB), 0, st, m, j);
   }
 }
@@ -547,15 +550,16 @@ static size_t eig_lds() {
 }
 
 template <typename T> void mps_sweep_rl(const MpsDev &m, int l, int r, hipStream_t st) {
+  const int wm = m.wmul;
   for (int j = r; j > l; --j) {
-    int L = 2 * dmax(m, j, 1);
+    int L = wm * dmax(m, j, 1);
     int nn = 2 * dmax(m, j + 1, 1);
     KLAUNCH(K_GRAM, k_gram<T>, gemm_grid(nn, nn, m.S), dim3(TB), 0, st, m, j);
     KLAUNCH(K_EIGEN, k_eig<T>, dim3(m.S), dim3(TB), eig_lds(), st, m, j);
     KLAUNCH(K_SELECT, k_select<T>, dim3(m.S), dim3(TB), 0, st, m, j);
     int kmax = dmax(m, j, 1);
     KLAUNCH(K_GEMM, k_ngemm<T>, gemm_grid(L, kmax, m.S), dim3(TB), 0, st, m, j);
-    int M = 2 * (j - 1 == l ? dmax(m, j - 1, 1) : 2 * dmax(m, j - 1, 1));
+    int M = 2 * (j - 1 == l ? dmax(m, j - 1, 1) : wm * dmax(m, j - 1, 1));
     KLAUNCH(K_GEMM, k_xgemm<T>, gemm_grid(M, kmax, m.S), dim3(TB), 0, st, m, j);
   }
   KLAUNCH(K_SELECT, k_finish<T>, dim3(m.S), dim3(TB), 0, st, m, l);

@@ -41,7 +41,10 @@ _lib = None
 EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn_clifford",
            "stn_rotate", "stn_measure", "stn_logprob", "stn_sync", "stn_get_tableau",
            "stn_get_bonds", "stn_get_site", "stn_center", "stn_profile", "stn_profile_read",
-           "stn_set_site", "stn_set_center", "stn_set_layer_mode", "stn_set_layer_threads", "stn_reset"]
+           "stn_set_site", "stn_set_center", "stn_set_layer_mode", "stn_set_layer_threads", "stn_reset",
+           "stn_tape_bytes", "stn_tape_begin", "stn_tape_end", "stn_adjoint_bytes", "stn_adjoint_init",
+           "stn_adjoint_zero", "stn_backward", "stn_checkpoint_bytes", "stn_checkpoint_save",
+           "stn_checkpoint_load"]
 K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect", "layer"]
 
 
@@ -94,6 +97,26 @@ def load(path: str = LIB_PATH):
     lib.stn_set_layer_threads.restype = i32
     lib.stn_reset.restype = i32
     lib.stn_reset.argtypes = [vp]
+    lib.stn_tape_bytes.restype = ctypes.c_size_t
+    lib.stn_tape_bytes.argtypes = [vp, i32]
+    lib.stn_tape_begin.restype = i32
+    lib.stn_tape_begin.argtypes = [vp, vp, ctypes.c_size_t, i32]
+    lib.stn_tape_end.restype = i32
+    lib.stn_tape_end.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.stn_adjoint_bytes.restype = ctypes.c_size_t
+    lib.stn_adjoint_bytes.argtypes = [vp, i32]
+    lib.stn_adjoint_init.restype = i32
+    lib.stn_adjoint_init.argtypes = [vp, vp, ctypes.c_size_t, i32]
+    lib.stn_adjoint_zero.restype = i32
+    lib.stn_adjoint_zero.argtypes = [vp]
+    lib.stn_backward.restype = i32
+    lib.stn_backward.argtypes = [vp, vp, i64]
+    lib.stn_checkpoint_bytes.restype = ctypes.c_size_t
+    lib.stn_checkpoint_bytes.argtypes = [vp]
+    lib.stn_checkpoint_save.restype = i32
+    lib.stn_checkpoint_save.argtypes = [vp, vp]
+    lib.stn_checkpoint_load.restype = i32
+    lib.stn_checkpoint_load.argtypes = [vp, vp]
     lib.stn_set_layer_threads.argtypes = [vp, i32]
     _lib = lib
     return lib
@@ -220,6 +243,49 @@ class Simulator:
         """Initial state for every shot, by kernel launches only (capturable)."""
         self._check(self.lib.stn_reset(self.ctx))
 
+    # ------------------------------------------------------------ gradients
+    def _aligned(self, nbytes):
+        t = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        return t, (t.data_ptr() + 255) & ~255
+
+    def tape_begin(self, max_steps: int):
+        nb = self.lib.stn_tape_bytes(self.ctx, int(max_steps))
+        if nb == 0:
+            raise STNError(-1, "invalid tape size")
+        self._tape, ptr = self._aligned(nb)
+        self._check(self.lib.stn_tape_begin(self.ctx, ctypes.c_void_p(ptr), nb, int(max_steps)))
+
+    def tape_end(self) -> int:
+        nr = ctypes.c_int(0)
+        self._check(self.lib.stn_tape_end(self.ctx, ctypes.byref(nr)))
+        return nr.value
+
+    def adjoint_init(self, chi_adj: int):
+        nb = self.lib.stn_adjoint_bytes(self.ctx, int(chi_adj))
+        if nb == 0:
+            raise STNError(-1, "invalid adjoint bond cap")
+        self._adj, ptr = self._aligned(nb)
+        self._check(self.lib.stn_adjoint_init(self.ctx, ctypes.c_void_p(ptr), nb, int(chi_adj)))
+
+    def adjoint_zero(self):
+        self._check(self.lib.stn_adjoint_zero(self.ctx))
+
+    def backward(self, grad, col: int = 0):
+        """grad: float64 device tensor [S, R]; the tape's rotations go to
+        columns col, col + 1, ..."""
+        assert grad.dtype == self.torch.float64 and grad.is_contiguous() and grad.dim() == 2
+        ptr = grad.data_ptr() + 8 * int(col)
+        self._check(self.lib.stn_backward(self.ctx, ctypes.c_void_p(ptr), grad.shape[1]))
+
+    def checkpoint_save(self):
+        nb = self.lib.stn_checkpoint_bytes(self.ctx)
+        buf, ptr = self._aligned(nb)
+        self._check(self.lib.stn_checkpoint_save(self.ctx, ctypes.c_void_p(ptr)))
+        return (buf, ptr)
+
+    def checkpoint_load(self, ck):
+        self._check(self.lib.stn_checkpoint_load(self.ctx, ctypes.c_void_p(ck[1])))
+
     def tableau(self):
         """(x [2n, n] bool, z [2n, n] bool, sign [2n, S] bool)."""
         n = self.n
@@ -294,10 +360,11 @@ class Simulator:
 
 
 # ----------------------------------------------------------------- circuits
-def prepare(circ, device="cuda:0", forced: Optional[np.ndarray] = None):
+def prepare(circ, device="cuda:0", forced: Optional[np.ndarray] = None, per_shot_theta: bool = False):
     """Uploads every per-shot input of a workload Circuit to the device once
     (noise sign words, angles, measurement uniforms or forced outcomes).
-    forced: uint8 [S, n_measurements] or None."""
+    forced: uint8 [S, n_measurements] or None.  Angles shared by all shots
+    are uploaded once (stride 0) unless per_shot_theta."""
     import torch
     dev = torch.device(device)
     ops = []
@@ -311,7 +378,7 @@ def prepare(circ, device="cuda:0", forced: Optional[np.ndarray] = None):
             ops.append(("noise", torch.from_numpy(words.view(np.int64)).to(dev)))
         elif k == "rotate":
             th = np.ascontiguousarray(op["theta"], dtype=np.float64)
-            shared = bool(np.all(th == th[:1]))
+            shared = not per_shot_theta and bool(np.all(th == th[:1]))
             tdev = torch.from_numpy(th[0].copy() if shared else th).to(dev)
             ops.append(("rotate", np.ascontiguousarray(op["paulis"], np.int32), tdev,
                         0 if shared else th.shape[1]))

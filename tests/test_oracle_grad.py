@@ -89,6 +89,26 @@ def test_untruncated_gradient_is_physical(seed):
         assert abs(ga[i] - fd) <= 1e-7 * max(1.0, abs(fd)), (i, ga[i], fd)
 
 
+def test_d3_memory_gradient_is_physical():
+    """d=3 memory experiment (17 qubits), 2 rounds, Pauli noise, one angle per
+    rotation instance: sampled entries against statevector differences."""
+    from paper_2605_29514_amd import workload as W
+    circ = W.memory_circuit(3, 2, 1, seed=5, theta_nn=0.1, p=0.02, per_layer_params=True)
+    tape = G.record(circ, 0, 1 << 10, 1e-16)
+    ga = G.adjoint_gradient(tape)
+    rec = SV.run_shot(circ, 0)[0]
+    big = np.argsort(-np.abs(ga))[:4]
+    pick = list(big) + [int(i) for i in np.random.default_rng(0).choice(tape.n_rot, 4, replace=False)]
+    h = 1e-5
+    for i in pick:
+        t0 = _theta_of(circ, 0, i)
+        lp = SV.run_shot(_with_theta(circ, 0, i, t0 + h), 0, forced=rec)[3]
+        lm = SV.run_shot(_with_theta(circ, 0, i, t0 - h), 0, forced=rec)[3]
+        fd = (lp - lm) / (2 * h)
+        assert abs(ga[i] - fd) <= 1e-7 * max(1.0, abs(fd)), (i, ga[i], fd)
+    assert np.abs(ga).max() > 0.1
+
+
 def test_gradient_is_odd_in_theta():
     circ = entangling_circuit(8, 5, 1, 2, phase_gates=False)
     rec = SV.run_shot(circ, 0)[0]
