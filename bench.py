@@ -225,6 +225,7 @@ def main():
     ms = ev0.elapsed_time(ev1)
     sim.sync()
     prof = sim.profile_read()
+    phases = sim.profile_phases()
     lo, hi = rounds[W][0], rounds[W + K - 1][1]
     n_rot = rotations_in(ops, lo, hi) * circ.n_shots
     bonds = sim.bonds()
@@ -275,7 +276,9 @@ def main():
                    "shots": circ.n_shots, "chi_max": chi, "rotations_timed": n_rot,
                    "max_bond_after": int(bonds.max()), "mean_bond_after": float(bonds.mean()),
                    "wall_s": wall, "eigen_sweeps": prof["eigen_sweeps"], "schedule": schedule,
-                   "class_ms": {c: prof[c]["ms"] for c in classes}},
+                   "class_ms": {c: prof[c]["ms"] for c in classes},
+                   "layer_phase_share": ({k: v / sum(phases.values()) for k, v in phases.items()}
+                                         if sum(phases.values()) > 0 else None)},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -247,6 +247,14 @@ stn_status stn_profile_read(stn_ctx *ctx, double *host_ms, double *host_flops,
                             double *host_bytes, long long *host_launches,
                             double *host_eig_sweeps, double *host_layer_fp64_flops);
 
+/* Phases of the fused layer kernel, summed over shots in shader clock
+ * cycles while profiling is on (stn_profile with any class): 0 angle and
+ * single-site steps, 1 centre moves, 2 bond-2 blocks, 3 QR of the
+ * left-to-right sweep, 4 its R absorption, 5 FP64 Gram, 6 Jacobi
+ * eigen-solve, 7 selection, the two truncation products and the
+ * renormalisation.  host_cycles: 8 doubles.  Synchronises. */
+stn_status stn_profile_phases(stn_ctx *ctx, double *host_cycles);
+
 /* How stn_rotate schedules its kernels: 1 = one launch per kernel step for
  * all shots (grids spread each product over many blocks; best for few
  * shots), 2 = one launch per chunk of up to 64 rotations in which each block

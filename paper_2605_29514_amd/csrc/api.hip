@@ -235,6 +235,11 @@ void plan_mps(Layout &L, int n, int S, int chi, size_t esz, int wmul, char *base
          o_F = L.off((size_t)chi_eff * 2 * chi_eff * S * sizeof(c64));
   const int64_t Jcap = (int64_t)align_up(layer_fallback_bytes((int)chi_eff));
   size_t o_J = L.off((size_t)Jcap * S);
+  // environment path of the fused kernel (forward state only): one Gram per
+  // site of a span for doubled bonds up to eb
+  const int64_t eb = wmul == 2 ? std::min<int64_t>(kEnvBond, 2 * chi_eff) : 0;
+  const int64_t Escap = (int64_t)n * eb * eb, Fscap = eb * 2 * eb;
+  size_t o_Es = L.off((size_t)Escap * S * sizeof(c64)), o_Fs = L.off((size_t)Fscap * S * sizeof(c64));
   if (base) {
     MpsDev &m = *mp;
     m.n = n; m.S = S; m.chi = chi;
@@ -252,6 +257,9 @@ void plan_mps(Layout &L, int n, int S, int chi, size_t esz, int wmul, char *base
     m.E = (c64 *)(base + o_E); m.E_cap = chi_eff * chi_eff;
     m.F = (c64 *)(base + o_F); m.F_cap = chi_eff * 2 * chi_eff;
     m.J = base + o_J; m.J_cap = Jcap;
+    m.Es = (c64 *)(base + o_Es); m.Es_cap = Escap;
+    m.Fs = (c64 *)(base + o_Fs); m.Fs_cap = Fscap;
+    m.ebond = (int)eb;
     m.logp = (double *)(base + o_logp); m.fid = (double *)(base + o_fid);
     m.p0 = (double *)(base + o_p0); m.nrm = (double *)(base + o_nrm);
     m.pm = (double *)(base + o_pm); m.trunc = (int *)(base + o_tr);
@@ -287,7 +295,7 @@ size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> 
   size_t o_tab = L.off(64);
   size_t o_ops = L.off((size_t)n * 8 * sizeof(c64)), o_eops = L.off((size_t)n * 4 * sizeof(c64));
   size_t o_err = L.off(4);
-  size_t o_work = L.off((size_t)(2 * K_COUNT + 2) * 8);
+  size_t o_work = L.off((size_t)kWorkWords * 8);
   MpsDev *mp = ctx && base ? &ctx->mps : nullptr;
   plan_mps(L, n, S, chi, esz, 2, base && ctx ? base : nullptr, mp, offs);
   if (ctx && base) {
@@ -851,7 +859,7 @@ stn_status stn_profile(stn_ctx *c, unsigned class_mask) {
   c->prof.used = 0;
   for (int k = 0; k < K_COUNT; ++k) { c->prof_ms[k] = 0; c->prof_launches[k] = 0; }
   c->mps.prof = class_mask ? 1 : 0;
-  hipError_t e = hipMemsetAsync(c->mps.work, 0, (size_t)(2 * K_COUNT + 2) * 8, c->st);
+  hipError_t e = hipMemsetAsync(c->mps.work, 0, (size_t)kWorkWords * 8, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
 }
@@ -868,7 +876,7 @@ stn_status stn_profile_read(stn_ctx *c, double *ms, double *flops, double *bytes
   }
   c->prof.recs.clear();
   c->prof.used = 0;
-  double w[2 * K_COUNT + 2];
+  double w[kWorkWords];
   hipError_t e = hipMemcpy(w, c->mps.work, sizeof(w), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
   for (int k = 0; k < K_COUNT; ++k) {
@@ -977,6 +985,14 @@ stn_status stn_set_site(stn_ctx *c, int shot, int site, const void *buf, int dl,
   int b[2] = {dl, dr};
   if (e == hipSuccess)
     e = hipMemcpy(c->mps.bond + (size_t)shot * (c->n + 1) + site, b, 8, hipMemcpyHostToDevice);
+  return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
+}
+
+stn_status stn_profile_phases(stn_ctx *c, double *cycles) {
+  if (!c || !cycles) return STN_EINVAL;
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  hipError_t e = hipMemcpy(cycles, c->mps.work + kPhaseBase, kPhases * 8, hipMemcpyDeviceToHost);
   return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
 }
 

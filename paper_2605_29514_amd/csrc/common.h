@@ -44,6 +44,12 @@ __host__ __device__ inline cplx<D> cvt(cplx<S> a) { return {(D)a.x, (D)a.y}; }
 // ------------------------------------------------------------- profiling
 // Launch classes for timing and algorithmic work accounting.
 enum { K_TABLEAU = 0, K_BUILD, K_QR, K_GEMM, K_GRAM, K_EIGEN, K_SELECT, K_EXPECT, K_LAYER, K_COUNT };
+// Device work counters: [K_COUNT][2] flops/bytes, Jacobi sweeps, layer FP64
+// flops, then the fused kernel's per-phase cycle totals.
+constexpr int kPhaseBase = 2 * K_COUNT + 2, kPhases = 8, kWorkWords = kPhaseBase + kPhases;
+// Largest doubled bond for which the fused kernel keeps the left-environment
+// Grams of a span (64 x 64 FP64 complex each) instead of a QR sweep.
+constexpr int kEnvBond = 64;
 
 // Host-side recorder: when active, launches of the selected classes are
 // bracketed by HIP events on their stream.
@@ -123,6 +129,9 @@ struct MpsDev {
   c64 *E;    int64_t E_cap;     // transfer matrix (FP64)
   c64 *F;    int64_t F_cap;
   void *J;   int64_t J_cap;     // bytes: fused-kernel fallbacks (reflectors, Jacobi pairs)
+  c64 *Es;   int64_t Es_cap;    // fused kernel: left-environment Grams of a span (FP64)
+  c64 *Fs;   int64_t Fs_cap;    //               and their product scratch
+  int ebond;                    // largest workspace bond the environment path accepts
   double *logp, *fid, *p0, *nrm;  // [S]
   double *pm;                   // [S] probability of the last recorded outcome
   int *trunc;                   // [S] set when chi_max dropped weight above the cut

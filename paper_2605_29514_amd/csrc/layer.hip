@@ -139,6 +139,19 @@ __device__ inline void rot_site_ops(const uint64_t *bx, const uint64_t *bz, int 
   site_op(bitw(bx, j), bitw(bz, j), o2);
 }
 
+// Per-phase cycle accounting (thread 0, profiling runs only).
+struct PhaseClock {
+  bool on;
+  long long t;
+  __device__ explicit PhaseClock(bool o) : on(o), t(o ? clock64() : 0) {}
+  __device__ void lap(const MpsDev &m, int k) {
+    if (!on) return;
+    const long long now = clock64();
+    atomicAdd(&m.work[kPhaseBase + k], (double)(now - t));
+    t = now;
+  }
+};
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, const uint64_t *psgn,
                                               int W, int SW, const double *theta, int64_t stride,
@@ -149,6 +162,7 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
   __shared__ c64 cf[2];
   __shared__ int sweeps;
   int c = L.center_in;
+  PhaseClock clk(m.prof && tid == 0);
   for (int i = 0; i < L.n_rot; ++i) {
     const int l = L.l[i], r = L.r[i];
     const uint64_t *bx = pbits + (size_t)i * 2 * W, *bz = bx + W;
@@ -173,17 +187,30 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
         A[(size_t)(a * 2 + 1) * dr + cc] = cvt<T>(ca * x1 + cb * (o2[2] * x0 + o2[3] * x1));
       }
       __syncthreads();
+      clk.lap(m, 0);
       continue;
     }
+    clk.lap(m, 0);
     while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
     while (c > r) { blk_move_left<T, NT>(m, s, c, lds); --c; }
+    clk.lap(m, 1);
+    // Environment path: when every doubled bond of the span fits the
+    // shot's Gram store, the left-to-right sweep forms the left-environment
+    // Grams E_j = sum_s B_j^s^H E_{j-1} B_j^s (FP64) instead of a QR sweep,
+    // and the truncation uses rho = X^H E X, the same reduced density that
+    // X^H X gives after orthonormalisation.  Otherwise: Householder QR.
+    bool env = m.ebond > 0;
+    for (int j = l; j <= r && env; ++j) {
+      const int Dl = (j == l) ? b[j] : 2 * b[j], Dr = (j == r) ? b[j + 1] : 2 * b[j + 1];
+      env = Dl <= m.ebond && Dr <= m.ebond;
+    }
     // bond-2 blocks over [l, r]
     for (int j = l; j <= r; ++j) {
       const int dl = b[j], dr = b[j + 1];
       const int Dl = (j == l) ? dl : 2 * dl, Dr = (j == r) ? dr : 2 * dr;
       c64 o2[4];
       rot_site_ops(bx, bz, j, o2);
-      cplx<T> *out = (j == l) ? scr<T>(m.T, m.T_cap, s) : wslot<T>(m, j, s);
+      cplx<T> *out = (j == l && !env) ? scr<T>(m.T, m.T_cap, s) : wslot<T>(m, j, s);
       const cplx<T> *A = slot<T>(m, j, s);
       for (int e = tid; e < Dl * Dr; e += NT) {
         const int a = e / Dr, cc = e % Dr;
@@ -207,13 +234,42 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
       if (tid == 0) { w[j] = Dl; if (j == r) w[r + 1] = dr; }
     }
     __syncthreads();
+    clk.lap(m, 2);
+    c64 *Es = m.Es + (size_t)s * m.Es_cap, *Fs = m.Fs + (size_t)s * m.Fs_cap;
+    const int eb2 = m.ebond * m.ebond;
+    if (env) {
+      // E_l = B_l^H B_l (B_l as 2 w[l] x w[l+1]); then E_j through site r-1
+      {
+        const int D = w[l + 1], K = 2 * w[l];
+        blk_gemm<T, T, double, double, NT>(D, D, K, wslot<T>(m, l, s), D, 1, wslot<T>(m, l, s), D, 0, Es, D, lds);
+        if (tid == 0) {
+          add_work(m, K_LAYER, gemm_flops(D, D, K), (double)sizeof(cplx<T>) * K * D + 16.0 * D * D);
+          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(D, D, K));
+        }
+      }
+      for (int j = l + 1; j < r; ++j) {
+        const int Dl = w[j], Dr = w[j + 1];
+        c64 *Ep = Es + (size_t)(j - 1 - l) * eb2, *Ej = Es + (size_t)(j - l) * eb2;
+        blk_gemm<double, T, double, double, NT>(Dl, 2 * Dr, Dl, Ep, Dl, 0, wslot<T>(m, j, s), 2 * Dr, 0, Fs, 2 * Dr, lds);
+        blk_gemm<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, Fs, Dr, 0, Ej, Dr, lds);
+        if (tid == 0) {
+          const double f = gemm_flops(Dl, 2 * Dr, Dl) + gemm_flops(Dr, Dr, 2 * Dl);
+          add_work(m, K_LAYER, f, (double)sizeof(cplx<T>) * 2 * Dl * Dr + 16.0 * (Dl * Dl + 2.0 * Dl * Dr + Dr * Dr));
+          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f);
+        }
+      }
+      blk_copy<T, NT>(scr<T>(m.T, m.T_cap, s), wslot<T>(m, r, s), 2 * w[r] * w[r + 1]);
+      clk.lap(m, 3);
+    }
     // left-to-right QR sweep: B_j = Q R, Q -> workspace slot j, R B_{j+1} -> T
-    for (int j = l; j < r; ++j) {
+    for (int j = l; j < r && !env; ++j) {
       const int rows = 2 * w[j], cols = w[j + 1], N = 2 * w[j + 2];
       const int p = rows < cols ? rows : cols;
       cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
       blk_qr<T, NT>(m, s, rows, cols, X, wslot<T>(m, j, s), 0, R, lds);
+      clk.lap(m, 3);
       blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, wslot<T>(m, j + 1, s), N, 0, X, N, lds);
+      clk.lap(m, 4);
       if (tid == 0) {
         w[j + 1] = p;
         add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
@@ -226,7 +282,18 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
       const int Lx = w[j], nn = 2 * w[j + 1];
       cplx<T> *X = scr<T>(m.T, m.T_cap, s);
       c64 *Gg = m.G + s * m.G_cap;
-      blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
+      if (env) {                              // rho = X^H (E_{j-1} X)
+        const c64 *Ep = Es + (size_t)(j - 1 - l) * eb2;
+        blk_gemm<double, T, double, double, NT>(Lx, nn, Lx, Ep, Lx, 0, X, nn, 0, Fs, nn, lds);
+        blk_gemm<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, Fs, nn, 0, Gg, nn, lds);
+        if (tid == 0) {
+          add_work(m, K_LAYER, gemm_flops(Lx, nn, Lx), 16.0 * (Lx * Lx + Lx * nn));
+          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(Lx, nn, Lx));
+        }
+      } else {
+        blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
+      }
+      clk.lap(m, 5);
       {
         const Fallback f = fallback(m, s);
         const bool lp = nn <= kLdsPairs;
@@ -251,6 +318,7 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
           if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
           if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)sweeps);
         }
+        clk.lap(m, 6);
       }
       cplx<T> *Vt = scr<T>(m.Vt, m.Vt_cap, s);
       const int k = select_body<T, NT>(m, s, j, Vt);
@@ -266,6 +334,7 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
       __syncthreads();
     }
     finish_body<T, NT>(m, s, l, scr<T>(m.T, m.T_cap, s));
+    clk.lap(m, 7);
     c = l;
   }
 }

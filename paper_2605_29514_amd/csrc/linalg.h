@@ -321,29 +321,62 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
         pp[i] = p; pq[i] = q; pc[i] = cs; ps[i] = sn; pe[i] = eph;
       }
       __syncthreads();
-      // rows p, q <- U^H rows
-      for (int e = tid; e < (P / 2) * nn; e += NT) {
-        int i = e / nn, col = e % nn;
-        if (ps[i] == 0) continue;
-        int p = pp[i], q = pq[i];
-        c64 gp = G[(size_t)p * nn + col], gq = G[(size_t)q * nn + col];
-        double cs = pc[i], sn = ps[i];
-        c64 eq = pe[i] * gq;
-        G[(size_t)p * nn + col] = cs * gp - sn * eq;
-        G[(size_t)q * nn + col] = sn * gp + cs * eq;
+      // G <- U^H G U and V <- V U in one pass.  The pairs are disjoint and
+      // cover every index, so G splits into 2x2 blocks (rows of pair i,
+      // columns of pair k) that transform independently:
+      // block <- L_i block R_k with L_i (x_p, x_q) = (cs x_p - sn e x_q,
+      // sn x_p + cs e x_q) and R_k the same with conj(e) on row vectors.
+      // G stays Hermitian, so only blocks i <= k are computed and mirrored.
+      const int H = P / 2;
+      for (int e = tid; e < H * H; e += NT) {
+        const int i = e / H, k = e % H;
+        if (i > k) continue;
+        const bool ri = ps[i] != 0, rk = ps[k] != 0;
+        if (!ri && !rk) continue;
+        const int rp = pp[i], rq = pq[i], cp = pp[k], cq = pq[k];
+        const bool vq = rq < nn, wq = cq < nn;
+        c64 b00 = G[(size_t)rp * nn + cp];
+        c64 b01 = wq ? G[(size_t)rp * nn + cq] : mk<double>(0, 0);
+        c64 b10 = vq ? G[(size_t)rq * nn + cp] : mk<double>(0, 0);
+        c64 b11 = (vq && wq) ? G[(size_t)rq * nn + cq] : mk<double>(0, 0);
+        if (ri) {
+          const double cs = pc[i], sn = ps[i];
+          const c64 ei = pe[i];
+          const c64 t10 = ei * b10, t11 = ei * b11;
+          const c64 n00 = cs * b00 - sn * t10, n01 = cs * b01 - sn * t11;
+          b10 = sn * b00 + cs * t10;
+          b11 = sn * b01 + cs * t11;
+          b00 = n00;
+          b01 = n01;
+        }
+        if (rk) {
+          const double cs = pc[k], sn = ps[k];
+          const c64 ek = cj(pe[k]);
+          const c64 t01 = ek * b01, t11 = ek * b11;
+          const c64 n00 = cs * b00 - sn * t01, n10 = cs * b10 - sn * t11;
+          b01 = sn * b00 + cs * t01;
+          b11 = sn * b10 + cs * t11;
+          b00 = n00;
+          b10 = n10;
+        }
+        G[(size_t)rp * nn + cp] = b00;
+        if (wq) G[(size_t)rp * nn + cq] = b01;
+        if (vq) G[(size_t)rq * nn + cp] = b10;
+        if (vq && wq) G[(size_t)rq * nn + cq] = b11;
+        if (i != k) {                         // mirror: block (k, i) = block (i, k)^H
+          G[(size_t)cp * nn + rp] = cj(b00);
+          if (vq) G[(size_t)cp * nn + rq] = cj(b10);
+          if (wq) G[(size_t)cq * nn + rp] = cj(b01);
+          if (vq && wq) G[(size_t)cq * nn + rq] = cj(b11);
+        }
       }
-      __syncthreads();
-      // columns p, q <- cols U (and the same for V)
-      for (int e = tid; e < (P / 2) * nn; e += NT) {
-        int i = e / nn, row = e % nn;
-        if (ps[i] == 0) continue;
-        int p = pp[i], q = pq[i];
-        double cs = pc[i], sn = ps[i];
-        c64 ec = cj(pe[i]);
-        c64 gp = G[(size_t)row * nn + p], gq = ec * G[(size_t)row * nn + q];
-        G[(size_t)row * nn + p] = cs * gp - sn * gq;
-        G[(size_t)row * nn + q] = sn * gp + cs * gq;
-        c64 vp = V[(size_t)row * nn + p], vq = ec * V[(size_t)row * nn + q];
+      for (int e = tid; e < H * nn; e += NT) {
+        const int k = e / nn, row = e % nn;
+        if (ps[k] == 0) continue;
+        const int p = pp[k], q = pq[k];
+        const double cs = pc[k], sn = ps[k];
+        const c64 ec = cj(pe[k]);
+        const c64 vp = V[(size_t)row * nn + p], vq = ec * V[(size_t)row * nn + q];
         V[(size_t)row * nn + p] = cs * vp - sn * vq;
         V[(size_t)row * nn + q] = sn * vp + cs * vq;
       }

@@ -44,7 +44,7 @@ EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn
            "stn_set_site", "stn_set_center", "stn_set_layer_mode", "stn_set_layer_threads", "stn_reset",
            "stn_tape_bytes", "stn_tape_begin", "stn_tape_end", "stn_adjoint_bytes", "stn_adjoint_init",
            "stn_adjoint_zero", "stn_backward", "stn_checkpoint_bytes", "stn_checkpoint_save",
-           "stn_checkpoint_load"]
+           "stn_checkpoint_load", "stn_profile_phases"]
 K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect", "layer"]
 
 
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH):
     lib.stn_adjoint_zero.argtypes = [vp]
     lib.stn_backward.restype = i32
     lib.stn_backward.argtypes = [vp, vp, i64]
+    lib.stn_profile_phases.restype = i32
+    lib.stn_profile_phases.argtypes = [vp, vp]
     lib.stn_checkpoint_bytes.restype = ctypes.c_size_t
     lib.stn_checkpoint_bytes.argtypes = [vp]
     lib.stn_checkpoint_save.restype = i32
@@ -349,6 +351,13 @@ class Simulator:
         out["eigen_sweeps"] = float(sw[0])
         out["layer_fp64_flops"] = float(f64[0])
         return out
+
+    def profile_phases(self) -> dict:
+        """Fused-kernel phase cycle totals (see stn_profile_phases)."""
+        out = np.zeros(8, np.float64)
+        self._check(self.lib.stn_profile_phases(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
+        names = ["angles_single", "moves", "build", "lr_qr", "lr_absorb", "gram", "eigen", "select_trunc"]
+        return dict(zip(names, out.tolist()))
 
     def set_layer_mode(self, mode: int):
         """0 automatic, 1 per-step kernels, 2 fused per-shot layer kernel."""
