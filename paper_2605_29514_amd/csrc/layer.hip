@@ -28,7 +28,7 @@ constexpr int kLdsPairs = 64;             // Jacobi pair tables in LDS up to thi
 
 // Dynamic LDS layout (bytes).  U: union of the phase operands.
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kU = cmax(cmax(2 * kLdsEigN * kLdsEigN * sizeof(c64), kLdsQrMat), GemmStage<double>::bytes);
+constexpr size_t kU = cmax(cmax(2 * kLdsEigN * (kLdsEigN + 1) * sizeof(c64), kLdsQrMat), GemmStage<double>::bytes);
 constexpr size_t kVs = kU;                                    // c64[kLdsQrRows]
 constexpr size_t kVd = kVs + kLdsQrRows * sizeof(c64);       // double[2 kLdsQrRows]
 constexpr size_t kPe = kVd + 2 * kLdsQrRows * sizeof(double);  // c64[kLdsPairs/2 + 1]
@@ -304,13 +304,19 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
         double *ps = lp ? reinterpret_cast<double *>(lds + kPs) : f.ps;
         c64 *pe = lp ? reinterpret_cast<c64 *>(lds + kPe) : f.pe;
         c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
-        if (nn <= kLdsEigN) {                 // rotate in LDS, write the sorted vectors back
+        int ldw = nn;
+        if (nn <= kLdsEigN) {                 // rotate in LDS (rows padded), write the sorted vectors back
           c64 *Gl = reinterpret_cast<c64 *>(lds);
-          blk_copy<double, NT>(Gl, Gg, nn * nn);
+          ldw = nn + 1;
+          for (int e = tid; e < nn * nn; e += NT) {
+            const int r0 = e / nn, c0 = e - r0 * nn;
+            Gl[r0 * ldw + c0] = Gg[e];
+          }
+          __syncthreads();
           Gw = Gl;
-          Vw = Gl + kLdsEigN * kLdsEigN;
+          Vw = Gl + kLdsEigN * (kLdsEigN + 1);
         }
-        jacobi_block<NT>(nn, Gw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, &sweeps,
+        jacobi_block<NT>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, &sweeps,
                          sizeof(T) == 8 ? 1e-18 : 1e-16, sizeof(T) == 8 ? 1e-15 : 1e-13);
         if (tid == 0) {
           const double f64 = gemm_flops(nn, nn, Lx) + 36.0 * nn * nn * (double)nn;

@@ -275,22 +275,27 @@ __device__ void qr_block(int m, int nc, cplx<T> *A, cplx<T> *Qd, int qt, cplx<T>
 // order -- index 0 fixed, the others shifted by one place per round; the
 // 2x2 block [[a, c], [c*, b]] is diagonalised by U = diag(1, e^{-i phi}) R
 // with c = |c| e^{i phi} and R the real symmetric Jacobi rotation.
+// G and the rotation accumulator V use leading dimension ld (>= nn; one
+// more than nn staggers LDS rows across banks); Vout uses nn.
 // Scratch: pos (nn + 1 ints), pp/pq (nn/2 + 1 ints), pc/ps (nn/2 + 1
 // doubles), pe (nn/2 + 1 complex doubles).
 template <int NT>
-__device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int *err, int *pos,
+__device__ void jacobi_block(int nn, c64 *G, int ld, c64 *V, double *ev, c64 *Vout, int *err, int *pos,
                              double *pc, double *ps, c64 *pe, int *pp, int *pq, int *sweeps_out,
                              double abs_tol, double rel_tol) {
   const int tid = threadIdx.x;
   const int P = nn + (nn & 1);
-  for (int e = tid; e < nn * nn; e += NT) V[e] = mk<double>((e / nn) == (e % nn) ? 1.0 : 0.0, 0);
+  for (int e = tid; e < nn * nn; e += NT) {
+    const int r0 = e / nn, c0 = e - r0 * nn;
+    V[(size_t)r0 * ld + c0] = mk<double>(r0 == c0 ? 1.0 : 0.0, 0);
+  }
   // The Gram matrix is positive semi-definite, so its trace bounds every
   // eigenvalue and is invariant under the rotations.  An entry G_pq is
   // negligible when |G_pq| <= max(abs_tol tr, rel_tol sqrt(G_pp G_qq)): the
   // relative part keeps small kept eigenvalues from mixing with the (near)
   // null space, the absolute floor stops at the rounding level of the Gram.
   double trp = 0;
-  for (int i = tid; i < nn; i += NT) trp += G[(size_t)i * nn + i].x;
+  for (int i = tid; i < nn; i += NT) trp += G[(size_t)i * ld + i].x;
   const double tr = bsum<NT>(trp);
   __syncthreads();
   const double afl = abs_tol * tr;
@@ -298,23 +303,36 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
   bool converged = nn <= 1 || !(tr > 0);
   int sweeps_done = 0;
   double last_off = 0;
+  // strides of the incremental task indices below (NT = st_i H + st_k, ...)
+  const int Hh = P / 2 > 0 ? P / 2 : 1;
+  const int st_i = NT / Hh, st_k = NT - (NT / Hh) * Hh;
+  const int sv_k = nn > 0 ? NT / nn : 0, sv_r = nn > 0 ? NT - (NT / nn) * nn : 0;
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
     for (int rnd = 0; rnd < P - 1; ++rnd) {
       for (int i = tid; i < P / 2; i += NT) {
-        int p = i == 0 ? 0 : 1 + ((i - 1 - rnd) % (P - 1) + (P - 1)) % (P - 1);
-        int q = 1 + ((P - 2 - i - rnd) % (P - 1) + (P - 1)) % (P - 1);
+        // positions 1..P-1 shift by one per round (circle method), 0 stays
+        int x = i - 1 - rnd, y = P - 2 - i - rnd;
+        if (x < 0) x += P - 1;
+        if (y < 0) y += P - 1;
+        int p = i == 0 ? 0 : 1 + x;
+        int q = 1 + y;
         if (p > q) { int t = p; p = q; q = t; }
         double cs = 1, sn = 0;
         c64 eph = mk<double>(1, 0);
         if (q < nn) {
-          c64 c = G[(size_t)p * nn + q];
-          double h = sqrt(norm2(c));
-          double a = G[(size_t)p * nn + p].x, b = G[(size_t)q * nn + q].x;
+          const c64 c = G[(size_t)p * ld + q];
+          const double h2 = norm2(c);
+          const double a = G[(size_t)p * ld + p].x, b = G[(size_t)q * ld + q].x;
+          const double h = sqrt(h2);
           if (h > afl && h > rel_tol * sqrt(fabs(a * b))) {
-            eph = mk<double>(c.x / h, c.y / h);
-            double tau = (b - a) / (2 * h);
-            double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1 + tau * tau));
-            cs = 1 / sqrt(1 + t * t);
+            // t = tan of the rotation angle, the root of t^2 + 2 tau t - 1 = 0
+            // of smaller modulus with tau = (b - a) / 2h, written without tau:
+            // t = sign(d) 2h / (|d| + sqrt(d^2 + 4 h^2)), d = b - a
+            const double d = b - a;
+            const double t = (d >= 0 ? 2.0 : -2.0) * h / (fabs(d) + sqrt(d * d + 4.0 * h2));
+            const double ih = 1.0 / h;
+            eph = mk<double>(c.x * ih, c.y * ih);
+            cs = 1.0 / sqrt(1.0 + t * t);
             sn = t * cs;
           }
         }
@@ -328,17 +346,20 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
       // sn x_p + cs e x_q) and R_k the same with conj(e) on row vectors.
       // G stays Hermitian, so only blocks i <= k are computed and mirrored.
       const int H = P / 2;
-      for (int e = tid; e < H * H; e += NT) {
-        const int i = e / H, k = e % H;
+      // (i, k) of task e = i H + k advanced incrementally (no division)
+      int bi = tid / H, bk = tid - (tid / H) * H;
+      for (int e = tid; e < H * H; e += NT, bi += st_i, bk += st_k) {
+        if (bk >= H) { bk -= H; ++bi; }
+        const int i = bi, k = bk;
         if (i > k) continue;
         const bool ri = ps[i] != 0, rk = ps[k] != 0;
         if (!ri && !rk) continue;
         const int rp = pp[i], rq = pq[i], cp = pp[k], cq = pq[k];
         const bool vq = rq < nn, wq = cq < nn;
-        c64 b00 = G[(size_t)rp * nn + cp];
-        c64 b01 = wq ? G[(size_t)rp * nn + cq] : mk<double>(0, 0);
-        c64 b10 = vq ? G[(size_t)rq * nn + cp] : mk<double>(0, 0);
-        c64 b11 = (vq && wq) ? G[(size_t)rq * nn + cq] : mk<double>(0, 0);
+        c64 b00 = G[(size_t)rp * ld + cp];
+        c64 b01 = wq ? G[(size_t)rp * ld + cq] : mk<double>(0, 0);
+        c64 b10 = vq ? G[(size_t)rq * ld + cp] : mk<double>(0, 0);
+        c64 b11 = (vq && wq) ? G[(size_t)rq * ld + cq] : mk<double>(0, 0);
         if (ri) {
           const double cs = pc[i], sn = ps[i];
           const c64 ei = pe[i];
@@ -359,26 +380,28 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
           b00 = n00;
           b10 = n10;
         }
-        G[(size_t)rp * nn + cp] = b00;
-        if (wq) G[(size_t)rp * nn + cq] = b01;
-        if (vq) G[(size_t)rq * nn + cp] = b10;
-        if (vq && wq) G[(size_t)rq * nn + cq] = b11;
+        G[(size_t)rp * ld + cp] = b00;
+        if (wq) G[(size_t)rp * ld + cq] = b01;
+        if (vq) G[(size_t)rq * ld + cp] = b10;
+        if (vq && wq) G[(size_t)rq * ld + cq] = b11;
         if (i != k) {                         // mirror: block (k, i) = block (i, k)^H
-          G[(size_t)cp * nn + rp] = cj(b00);
-          if (vq) G[(size_t)cp * nn + rq] = cj(b10);
-          if (wq) G[(size_t)cq * nn + rp] = cj(b01);
-          if (vq && wq) G[(size_t)cq * nn + rq] = cj(b11);
+          G[(size_t)cp * ld + rp] = cj(b00);
+          if (vq) G[(size_t)cp * ld + rq] = cj(b10);
+          if (wq) G[(size_t)cq * ld + rp] = cj(b01);
+          if (vq && wq) G[(size_t)cq * ld + rq] = cj(b11);
         }
       }
-      for (int e = tid; e < H * nn; e += NT) {
-        const int k = e / nn, row = e % nn;
+      int vk = tid / nn, vr = tid - (tid / nn) * nn;
+      for (int e = tid; e < H * nn; e += NT, vk += sv_k, vr += sv_r) {
+        if (vr >= nn) { vr -= nn; ++vk; }
+        const int k = vk, row = vr;
         if (ps[k] == 0) continue;
         const int p = pp[k], q = pq[k];
         const double cs = pc[k], sn = ps[k];
         const c64 ec = cj(pe[k]);
-        const c64 vp = V[(size_t)row * nn + p], vq = ec * V[(size_t)row * nn + q];
-        V[(size_t)row * nn + p] = cs * vp - sn * vq;
-        V[(size_t)row * nn + q] = sn * vp + cs * vq;
+        const c64 vp = V[(size_t)row * ld + p], vq = ec * V[(size_t)row * ld + q];
+        V[(size_t)row * ld + p] = cs * vp - sn * vq;
+        V[(size_t)row * ld + q] = sn * vp + cs * vq;
       }
       __syncthreads();
     }
@@ -386,9 +409,9 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
     for (int e = tid; e < nn * nn; e += NT) {
       const int p = e / nn, q = e % nn;
       if (p == q) continue;
-      const double h = sqrt(norm2(G[e]));
+      const double h = sqrt(norm2(G[(size_t)p * ld + q]));
       off = fmax(off, h);
-      if (h > afl && h > rel_tol * sqrt(fabs(G[(size_t)p * nn + p].x * G[(size_t)q * nn + q].x))) viol = 1;
+      if (h > afl && h > rel_tol * sqrt(fabs(G[(size_t)p * ld + p].x * G[(size_t)q * ld + q].x))) viol = 1;
     }
     off = bmax<NT>(off);
     viol = bmax<NT>(viol);
@@ -401,10 +424,10 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
   if (!converged && tid == 0 && last_off > 1e-10 * tr) atomicOr(err, STN_ERR_EIGEN);
   // sort descending: rank of each eigenvalue (ties by index)
   for (int i = tid; i < nn; i += NT) {
-    double li = G[(size_t)i * nn + i].x;
+    double li = G[(size_t)i * ld + i].x;
     int rank = 0;
     for (int j = 0; j < nn; ++j) {
-      double lj = G[(size_t)j * nn + j].x;
+      double lj = G[(size_t)j * ld + j].x;
       rank += (lj > li) || (lj == li && j < i);
     }
     ev[rank] = li;
@@ -413,7 +436,7 @@ __device__ void jacobi_block(int nn, c64 *G, c64 *V, double *ev, c64 *Vout, int 
   __syncthreads();
   for (int e = tid; e < nn * nn; e += NT) {
     int row = e / nn, col = e % nn;
-    Vout[(size_t)row * nn + pos[col]] = V[e];
+    Vout[(size_t)row * nn + pos[col]] = V[(size_t)row * ld + col];
   }
   __syncthreads();
 }

@@ -191,23 +191,25 @@ __global__ void k_eig(MpsDev m, int j) {
   const int s = blockIdx.x;
   const int nn = 2 * wbd(m, s)[j + 1];
   c64 *Gl = reinterpret_cast<c64 *>(lds);                 // used when nn <= kEigLdsN
-  c64 *Vl = Gl + kEigLdsN * kEigLdsN;
-  int *pos = reinterpret_cast<int *>(Vl + kEigLdsN * kEigLdsN);
+  c64 *Vl = Gl + kEigLdsN * (kEigLdsN + 1);
+  int *pos = reinterpret_cast<int *>(Vl + kEigLdsN * (kEigLdsN + 1));
   int *pp = pos + 1040, *pq = pp + 520;
   double *pc = reinterpret_cast<double *>(pq + 520);
   double *ps = pc + 520;
   c64 *pe = reinterpret_cast<c64 *>(ps + 520);
   c64 *Gg = m.G + s * m.G_cap;
   c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
-  if (nn <= kEigLdsN) {       // small matrices: rotate in LDS, write the sorted vectors back
-    for (int e = threadIdx.x; e < nn * nn; e += TB) Gl[e] = Gg[e];
+  int ldw = nn;
+  if (nn <= kEigLdsN) {       // small matrices: rotate in LDS (rows padded), write the sorted vectors back
+    ldw = nn + 1;
+    for (int e = threadIdx.x; e < nn * nn; e += TB) Gl[(e / nn) * ldw + e % nn] = Gg[e];
     __syncthreads();
     Gw = Gl;
     Vw = Vl;
   }
   // eigenvectors are accumulated in V and written sorted into G (global)
   __shared__ int sweeps;
-  jacobi_block<TB>(nn, Gw, Vw, m.ev + s * m.ev_cap, Gg,
+  jacobi_block<TB>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg,
                m.err, pos, pc, ps, pe, pp, pq, &sweeps,
                sizeof(T) == 8 ? 1e-18 : 1e-16, sizeof(T) == 8 ? 1e-15 : 1e-13);
   // algorithmic work: a Hermitian eigendecomposition with vectors, ~9 n^3 real
@@ -545,7 +547,7 @@ template <typename T> void mps_sweep_lr(const MpsDev &m, int l, int r, hipStream
 }
 
 static size_t eig_lds() {
-  return 2 * kEigLdsN * kEigLdsN * sizeof(c64) + 1040 * sizeof(int) + 2 * 520 * sizeof(int) +
+  return 2 * kEigLdsN * (kEigLdsN + 1) * sizeof(c64) + 1040 * sizeof(int) + 2 * 520 * sizeof(int) +
          2 * 520 * sizeof(double) + 520 * sizeof(c64);
 }
 
