@@ -194,16 +194,23 @@ stn_status stn_tape_begin(stn_ctx *ctx, void *dev_tape, size_t bytes, int max_st
  * receives the number of rotations recorded.  STN_ESTATE if not recording. */
 stn_status stn_tape_end(stn_ctx *ctx, int *n_rotations);
 
-/* Device bytes of the adjoint state with bond cap chi_adj (1..512); the
- * adjoint of a chi_max forward needs about 3 chi_max to stay exact. */
+/* Device bytes of the adjoint state with bond cap chi_adj (1..512).  The
+ * adjoint's Schmidt ranks can exceed the forward's; stn_adjoint_truncated
+ * reports when the cap was reached. */
 size_t stn_adjoint_bytes(const stn_ctx *ctx, int chi_adj);
 
 /* Places the adjoint state in dev_buf (caller-owned, 256-byte aligned, at
  * least stn_adjoint_bytes) and sets it to zero.  Synchronises. */
 stn_status stn_adjoint_init(stn_ctx *ctx, void *dev_buf, size_t bytes, int chi_adj);
 
-/* Sets the adjoint state to zero (start of a backward pass). */
+/* Sets the adjoint state to zero (start of a backward pass) and clears the
+ * flags of stn_adjoint_truncated. */
 stn_status stn_adjoint_zero(stn_ctx *ctx);
+
+/* Per shot (host_flags: n_shots ints), 1 when the adjoint state's bond cap
+ * dropped weight above the relative cut since stn_adjoint_zero: that shot's
+ * gradient is then approximate (raise chi_adj).  Synchronises. */
+stn_status stn_adjoint_truncated(stn_ctx *ctx, int *host_flags);
 
 /* Adjoint pass over the closed tape, last step first: writes dJ/dtheta of
  * the tape's i-th rotation for shot s to dev_grad[s * grad_stride + i]

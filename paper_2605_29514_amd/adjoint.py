@@ -64,7 +64,7 @@ class GradientRun:
         self.ops = stn.prepare(circ, device, forced=np.asarray(records, np.uint8), per_shot_theta=True)
         self.R = rotation_count(circ)
         self.segments = list(segments) if segments is not None else stretches(self.ops)
-        self.chi_adj = chi_adj or min(512, 3 * chi_max)
+        self.chi_adj = chi_adj or min(512, max(8 * chi_max, 64))
         self.checkpoints = []
         self.device = device
 
@@ -107,6 +107,7 @@ class GradientRun:
             if _steps_in(self.ops, a, b):
                 sim.backward(grad, col)
             col_end = col
+        self.adjoint_truncated = sim.adjoint_truncated()
         return grad
 
 

@@ -594,11 +594,19 @@ stn_status measure_impl(stn_ctx *c, const int32_t *qs, int n_meas, int reset, co
       if (ts != STN_OK) return ts;
     }
     launch_ops_measure(c->d_snap, c->W, l, r, piv, c->d_ops, c->d_eops, c->st);
-    move_center_into<T>(c, l, l);
-    mps_expect<T>(c->mps, l, r, c->d_eops, c->st);
-    launch_outcome(c->mps, c->d_snap + 2 * c->W, piv, r + 1, u, forced, n_meas, i, out, prob,
-                   c->d_negmask, c->d_mmask, c->st);
-    two_term<T>(c, l, r, false);
+    const bool fused = !c->taping && (c->layer_mode == 2 || (c->layer_mode == 0 && c->S >= 64));
+    if (fused) {                     // one per-shot launch: expectation, outcome, projection
+      MeasStep a{l, r, piv, c->center, n_meas, i};
+      mps_measure_fused<T>(c->mps, c->d_snap + 2 * c->W, c->d_ops, c->d_eops, a, u, forced, out, prob,
+                           c->d_negmask, c->d_mmask, c->layer_threads, c->st);
+      c->center = l;
+    } else {
+      move_center_into<T>(c, l, l);
+      mps_expect<T>(c->mps, l, r, c->d_eops, c->st);
+      launch_outcome(c->mps, c->d_snap + 2 * c->W, piv, r + 1, u, forced, n_meas, i, out, prob,
+                     c->d_negmask, c->d_mmask, c->st);
+      two_term<T>(c, l, r, false);
+    }
     if (c->taping) {
       stn_status ts = tape_post(c, rec, 1, l, r, piv);
       if (ts != STN_OK) return ts;
@@ -1079,8 +1087,18 @@ stn_status stn_adjoint_zero(stn_ctx *c) {
   if (!c || !c->adj_ready) return STN_ESTATE;
   if (c->prec == STN_FP64) mps_zero<double>(c->adj, c->st);
   else mps_zero<float>(c->adj, c->st);
+  launch_step_reset(c->adj, c->st);              // clears the per-shot cap flags
   c->adj_center = 0;
   return check_launch(c);
+}
+
+stn_status stn_adjoint_truncated(stn_ctx *c, int *host_flags) {
+  if (!c || !host_flags) return STN_EINVAL;
+  if (!c->adj_ready) return STN_ESTATE;
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  hipError_t e = hipMemcpy(host_flags, c->adj.trunc, (size_t)c->S * 4, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
 }
 
 stn_status stn_backward(stn_ctx *c, double *dev_grad, int64_t grad_stride) {

@@ -155,6 +155,16 @@ struct RotLayer {
   int16_t l[kProgBatch], r[kProgBatch];   // span of each rewritten Pauli
 };
 
+// One measurement of the fused per-shot path.
+struct MeasStep {
+  int l, r, pivot;              // span of P' and its first X/Y site (-1: none)
+  int center_in;                // orthogonality centre on entry
+  int n_meas, mi;               // row length of the record arrays and this column
+};
+template <typename T>
+void mps_measure_fused(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *d_ops, const c64 *d_eops,
+                       const MeasStep &a, const double *d_u, const uint8_t *d_forced, uint8_t *d_out,
+                       double *d_prob, uint64_t *d_negmask, uint64_t *d_mmask, int nt, hipStream_t st);
 template <typename T> hipError_t mps_prepare(int max_rows);
 template <typename T> hipError_t layer_prepare();
 size_t layer_fallback_bytes(int chi);

@@ -152,13 +152,228 @@ struct PhaseClock {
   }
 };
 
+// Site operators of one two-term step: a rotation takes O1 = I and O2 the
+// Pauli site operator from the bits of P'; a measurement projection reads
+// both from the operator table ops[(j - l) * 8 + {0..3, 4..7}].
+struct SiteOps {
+  const c64 *tab;
+  const uint64_t *bx, *bz;
+  int l;
+  __device__ void get(int j, c64 *o1, c64 *o2) const {
+    if (tab) {
+      for (int k = 0; k < 4; ++k) { o1[k] = tab[(size_t)(j - l) * 8 + k]; o2[k] = tab[(size_t)(j - l) * 8 + 4 + k]; }
+    } else {
+      site_op(0, 0, o1);
+      site_op(bitw(bx, j), bitw(bz, j), o2);
+    }
+  }
+};
+
+// One two-term step phi <- a O1 phi + b O2 phi over [l, r] for shot s, with
+// the centre tracked in c: bond-2 blocks, left-to-right sweep (environment
+// Grams or QR), right-to-left FP64 Gram/eigen truncation, FP64
+// renormalisation (the squared norm before it goes to nrm[s]).  A single
+// site is updated in place; a non-unitary one moves the centre there first
+// and renormalises.
+template <typename T, int NT>
+__device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &so, c64 ca, c64 cb, bool unitary,
+                          int &c, char *lds, PhaseClock &clk, int *sweeps) {
+  const int tid = threadIdx.x;
+  int *b = bnd(m, s), *w = wbd(m, s);
+  if (l == r) {
+    if (!unitary) {
+      while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
+      while (c > l) { blk_move_left<T, NT>(m, s, c, lds); --c; }
+    }
+    c64 o1[4], o2[4];
+    so.get(l, o1, o2);
+    const int dl = b[l], dr = b[l + 1];
+    cplx<T> *A = slot<T>(m, l, s);
+    double part = 0;
+    for (int e = tid; e < dl * dr; e += NT) {
+      const int a = e / dr, cc = e % dr;
+      const c64 x0 = cvt<double>(A[(size_t)(a * 2 + 0) * dr + cc]), x1 = cvt<double>(A[(size_t)(a * 2 + 1) * dr + cc]);
+      const c64 y0 = ca * (o1[0] * x0 + o1[1] * x1) + cb * (o2[0] * x0 + o2[1] * x1);
+      const c64 y1 = ca * (o1[2] * x0 + o1[3] * x1) + cb * (o2[2] * x0 + o2[3] * x1);
+      A[(size_t)(a * 2 + 0) * dr + cc] = cvt<T>(y0);
+      A[(size_t)(a * 2 + 1) * dr + cc] = cvt<T>(y1);
+      part += norm2(cvt<double>(cvt<T>(y0))) + norm2(cvt<double>(cvt<T>(y1)));
+    }
+    if (!unitary) {                           // FP64 renormalisation of the new centre
+      const double n2 = bsum<NT>(part);
+      if (!(n2 > 0) || isinf(n2)) {
+        if (tid == 0) atomicOr(m.err, STN_ERR_NUMERIC);
+      } else {
+        const double inv = 1.0 / sqrt(n2);
+        for (int e = tid; e < dl * 2 * dr; e += NT) A[e] = cvt<T>(inv * cvt<double>(A[e]));
+        if (tid == 0) m.nrm[s] = n2;
+      }
+    }
+    __syncthreads();
+    clk.lap(m, 0);
+    return;
+  }
+  clk.lap(m, 0);
+  while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
+  while (c > r) { blk_move_left<T, NT>(m, s, c, lds); --c; }
+  clk.lap(m, 1);
+  // Environment path: when every doubled bond of the span fits the shot's
+  // Gram store, the left-to-right sweep forms the left-environment Grams
+  // E_j = sum_s B_j^s^H E_{j-1} B_j^s (FP64) instead of a QR sweep, and the
+  // truncation uses rho = X^H E X, the same reduced density that X^H X gives
+  // after orthonormalisation.  Otherwise: Householder QR.
+  bool env = m.ebond > 0;
+  for (int j = l; j <= r && env; ++j) {
+    const int Dl = (j == l) ? b[j] : 2 * b[j], Dr = (j == r) ? b[j + 1] : 2 * b[j + 1];
+    env = Dl <= m.ebond && Dr <= m.ebond;
+  }
+  // bond-2 blocks over [l, r]
+  for (int j = l; j <= r; ++j) {
+    const int dl = b[j], dr = b[j + 1];
+    const int Dl = (j == l) ? dl : 2 * dl, Dr = (j == r) ? dr : 2 * dr;
+    c64 o1[4], o2[4];
+    so.get(j, o1, o2);
+    cplx<T> *out = (j == l && !env) ? scr<T>(m.T, m.T_cap, s) : wslot<T>(m, j, s);
+    const cplx<T> *A = slot<T>(m, j, s);
+    for (int e = tid; e < Dl * Dr; e += NT) {
+      const int a = e / Dr, cc = e % Dr;
+      const int ba = a >= dl, bc = cc >= dr;
+      int br = -1;
+      if (j == l) br = bc;
+      else if (j == r) br = ba;
+      else if (ba == bc) br = ba;
+      c64 y0 = mk<double>(0, 0), y1 = mk<double>(0, 0);
+      if (br >= 0) {
+        const int aa = (j == l) ? a : a - (ba ? dl : 0);
+        const int c2 = (j == r) ? cc : cc - (bc ? dr : 0);
+        const c64 x0 = cvt<double>(A[(size_t)(aa * 2 + 0) * dr + c2]), x1 = cvt<double>(A[(size_t)(aa * 2 + 1) * dr + c2]);
+        const c64 *o = br ? o2 : o1;
+        y0 = o[0] * x0 + o[1] * x1;
+        y1 = o[2] * x0 + o[3] * x1;
+        if (j == l) { const c64 k = br ? cb : ca; y0 = k * y0; y1 = k * y1; }
+      }
+      out[(size_t)(a * 2 + 0) * Dr + cc] = cvt<T>(y0);
+      out[(size_t)(a * 2 + 1) * Dr + cc] = cvt<T>(y1);
+    }
+    if (tid == 0) { w[j] = Dl; if (j == r) w[r + 1] = dr; }
+  }
+  __syncthreads();
+  clk.lap(m, 2);
+  c64 *Es = m.Es + (size_t)s * m.Es_cap, *Fs = m.Fs + (size_t)s * m.Fs_cap;
+  const int eb2 = m.ebond * m.ebond;
+  if (env) {
+    // E_l = B_l^H B_l (B_l as 2 w[l] x w[l+1]); then E_j through site r-1
+    {
+      const int D = w[l + 1], K = 2 * w[l];
+      blk_gemm<T, T, double, double, NT>(D, D, K, wslot<T>(m, l, s), D, 1, wslot<T>(m, l, s), D, 0, Es, D, lds);
+      if (tid == 0) {
+        add_work(m, K_LAYER, gemm_flops(D, D, K), (double)sizeof(cplx<T>) * K * D + 16.0 * D * D);
+        if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(D, D, K));
+      }
+    }
+    for (int j = l + 1; j < r; ++j) {
+      const int Dl = w[j], Dr = w[j + 1];
+      c64 *Ep = Es + (size_t)(j - 1 - l) * eb2, *Ej = Es + (size_t)(j - l) * eb2;
+      blk_gemm<double, T, double, double, NT>(Dl, 2 * Dr, Dl, Ep, Dl, 0, wslot<T>(m, j, s), 2 * Dr, 0, Fs, 2 * Dr, lds);
+      blk_gemm<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, Fs, Dr, 0, Ej, Dr, lds);
+      if (tid == 0) {
+        const double f = gemm_flops(Dl, 2 * Dr, Dl) + gemm_flops(Dr, Dr, 2 * Dl);
+        add_work(m, K_LAYER, f, (double)sizeof(cplx<T>) * 2 * Dl * Dr + 16.0 * (Dl * Dl + 2.0 * Dl * Dr + Dr * Dr));
+        if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f);
+      }
+    }
+    blk_copy<T, NT>(scr<T>(m.T, m.T_cap, s), wslot<T>(m, r, s), 2 * w[r] * w[r + 1]);
+    clk.lap(m, 3);
+  }
+  // left-to-right QR sweep: B_j = Q R, Q -> workspace slot j, R B_{j+1} -> T
+  for (int j = l; j < r && !env; ++j) {
+    const int rows = 2 * w[j], cols = w[j + 1], N = 2 * w[j + 2];
+    const int p = rows < cols ? rows : cols;
+    cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
+    blk_qr<T, NT>(m, s, rows, cols, X, wslot<T>(m, j, s), 0, R, lds);
+    clk.lap(m, 3);
+    blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, wslot<T>(m, j + 1, s), N, 0, X, N, lds);
+    clk.lap(m, 4);
+    if (tid == 0) {
+      w[j + 1] = p;
+      add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+      add_work(m, K_LAYER, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
+    }
+    __syncthreads();
+  }
+  // right-to-left truncation sweep
+  for (int j = r; j > l; --j) {
+    const int Lx = w[j], nn = 2 * w[j + 1];
+    cplx<T> *X = scr<T>(m.T, m.T_cap, s);
+    c64 *Gg = m.G + s * m.G_cap;
+    if (env) {                                // rho = X^H (E_{j-1} X)
+      const c64 *Ep = Es + (size_t)(j - 1 - l) * eb2;
+      blk_gemm<double, T, double, double, NT>(Lx, nn, Lx, Ep, Lx, 0, X, nn, 0, Fs, nn, lds);
+      blk_gemm<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, Fs, nn, 0, Gg, nn, lds);
+      if (tid == 0) {
+        add_work(m, K_LAYER, gemm_flops(Lx, nn, Lx), 16.0 * (Lx * Lx + Lx * nn));
+        if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(Lx, nn, Lx));
+      }
+    } else {
+      blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
+    }
+    clk.lap(m, 5);
+    {
+      const Fallback f = fallback(m, s);
+      const bool lp = nn <= kLdsPairs;
+      int *pos = lp ? reinterpret_cast<int *>(lds + kPos) : f.pos;
+      int *pp = lp ? reinterpret_cast<int *>(lds + kPp) : f.pp;
+      int *pq = lp ? reinterpret_cast<int *>(lds + kPq) : f.pq;
+      double *pc = lp ? reinterpret_cast<double *>(lds + kPc) : f.pc;
+      double *ps = lp ? reinterpret_cast<double *>(lds + kPs) : f.ps;
+      c64 *pe = lp ? reinterpret_cast<c64 *>(lds + kPe) : f.pe;
+      c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
+      int ldw = nn;
+      if (nn <= kLdsEigN) {                   // rotate in LDS (rows padded), write the sorted vectors back
+        c64 *Gl = reinterpret_cast<c64 *>(lds);
+        ldw = nn + 1;
+        for (int e = tid; e < nn * nn; e += NT) {
+          const int r0 = e / nn, c0 = e - r0 * nn;
+          Gl[r0 * ldw + c0] = Gg[e];
+        }
+        __syncthreads();
+        Gw = Gl;
+        Vw = Gl + kLdsEigN * (kLdsEigN + 1);
+      }
+      jacobi_block<NT>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, sweeps,
+                       jac_abs<T>(), jac_rel<T>());
+      if (tid == 0) {
+        const double f64 = gemm_flops(nn, nn, Lx) + 36.0 * nn * nn * (double)nn;
+        add_work(m, K_LAYER, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
+        if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
+        if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)*sweeps);
+      }
+      clk.lap(m, 6);
+    }
+    cplx<T> *Vt = scr<T>(m.Vt, m.Vt_cap, s);
+    const int k = select_body<T, NT>(m, s, j, Vt);
+    cplx<T> *Nn = scr<T>(m.N, m.N_cap, s);
+    blk_gemm<T, T, T, T, NT>(Lx, k, nn, X, nn, 0, Vt, k, 0, Nn, k, lds);
+    const int M = 2 * w[j - 1];
+    blk_gemm<T, T, T, T, NT>(M, k, Lx, wslot<T>(m, j - 1, s), Lx, 0, Nn, k, 0, X, k, lds);
+    if (tid == 0) {
+      w[j] = k;
+      add_work(m, K_LAYER, gemm_flops(Lx, k, nn) + gemm_flops(M, k, Lx),
+               (double)sizeof(cplx<T>) * ((double)Lx * nn + (double)nn * k + 2.0 * Lx * k + (double)M * Lx + (double)M * k));
+    }
+    __syncthreads();
+  }
+  finish_body<T, NT>(m, s, l, scr<T>(m.T, m.T_cap, s));
+  clk.lap(m, 7);
+  c = l;
+}
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, const uint64_t *psgn,
                                               int W, int SW, const double *theta, int64_t stride,
                                               RotLayer L) {
   extern __shared__ __align__(16) char lds[];
   const int s = blockIdx.x, tid = threadIdx.x;
-  int *b = bnd(m, s), *w = wbd(m, s);
   __shared__ c64 cf[2];
   __shared__ int sweeps;
   int c = L.center_in;
@@ -174,175 +389,96 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
       cf[1] = mk<double>(0, -sg * sin(th));
     }
     __syncthreads();
-    const c64 ca = cf[0], cb = cf[1];
-    if (l == r) {                              // unitary on one site: no bond change
-      c64 o2[4];
-      rot_site_ops(bx, bz, l, o2);
-      const int dl = b[l], dr = b[l + 1];
-      cplx<T> *A = slot<T>(m, l, s);
-      for (int e = tid; e < dl * dr; e += NT) {
-        const int a = e / dr, cc = e % dr;
-        c64 x0 = cvt<double>(A[(size_t)(a * 2 + 0) * dr + cc]), x1 = cvt<double>(A[(size_t)(a * 2 + 1) * dr + cc]);
-        A[(size_t)(a * 2 + 0) * dr + cc] = cvt<T>(ca * x0 + cb * (o2[0] * x0 + o2[1] * x1));
-        A[(size_t)(a * 2 + 1) * dr + cc] = cvt<T>(ca * x1 + cb * (o2[2] * x0 + o2[3] * x1));
-      }
-      __syncthreads();
-      clk.lap(m, 0);
-      continue;
-    }
-    clk.lap(m, 0);
-    while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
-    while (c > r) { blk_move_left<T, NT>(m, s, c, lds); --c; }
-    clk.lap(m, 1);
-    // Environment path: when every doubled bond of the span fits the
-    // shot's Gram store, the left-to-right sweep forms the left-environment
-    // Grams E_j = sum_s B_j^s^H E_{j-1} B_j^s (FP64) instead of a QR sweep,
-    // and the truncation uses rho = X^H E X, the same reduced density that
-    // X^H X gives after orthonormalisation.  Otherwise: Householder QR.
-    bool env = m.ebond > 0;
-    for (int j = l; j <= r && env; ++j) {
-      const int Dl = (j == l) ? b[j] : 2 * b[j], Dr = (j == r) ? b[j + 1] : 2 * b[j + 1];
-      env = Dl <= m.ebond && Dr <= m.ebond;
-    }
-    // bond-2 blocks over [l, r]
-    for (int j = l; j <= r; ++j) {
-      const int dl = b[j], dr = b[j + 1];
-      const int Dl = (j == l) ? dl : 2 * dl, Dr = (j == r) ? dr : 2 * dr;
-      c64 o2[4];
-      rot_site_ops(bx, bz, j, o2);
-      cplx<T> *out = (j == l && !env) ? scr<T>(m.T, m.T_cap, s) : wslot<T>(m, j, s);
-      const cplx<T> *A = slot<T>(m, j, s);
-      for (int e = tid; e < Dl * Dr; e += NT) {
-        const int a = e / Dr, cc = e % Dr;
-        const int ba = a >= dl, bc = cc >= dr;
-        int br = -1;
-        if (j == l) br = bc;
-        else if (j == r) br = ba;
-        else if (ba == bc) br = ba;
-        c64 y0 = mk<double>(0, 0), y1 = mk<double>(0, 0);
-        if (br >= 0) {
-          const int aa = (j == l) ? a : a - (ba ? dl : 0);
-          const int c2 = (j == r) ? cc : cc - (bc ? dr : 0);
-          c64 x0 = cvt<double>(A[(size_t)(aa * 2 + 0) * dr + c2]), x1 = cvt<double>(A[(size_t)(aa * 2 + 1) * dr + c2]);
-          if (br) { y0 = o2[0] * x0 + o2[1] * x1; y1 = o2[2] * x0 + o2[3] * x1; }
-          else { y0 = x0; y1 = x1; }
-          if (j == l) { const c64 k = br ? cb : ca; y0 = k * y0; y1 = k * y1; }
-        }
-        out[(size_t)(a * 2 + 0) * Dr + cc] = cvt<T>(y0);
-        out[(size_t)(a * 2 + 1) * Dr + cc] = cvt<T>(y1);
-      }
-      if (tid == 0) { w[j] = Dl; if (j == r) w[r + 1] = dr; }
+    const SiteOps so{nullptr, bx, bz, l};
+    shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], true, c, lds, clk, &sweeps);
+  }
+}
+
+// One Z measurement per shot (Sec. IV.A): centre to l, <phi|P'|phi> by FP64
+// transfer matrices over [l, r] (the centre norm N and tr E give
+// p(0) = (N + sigma tr E) / 2N), outcome m = 0 iff u < p(0) (or forced),
+// log P, then the projection as a two-term step (coefficients (1/2,
+// s sigma / 2) without a pivot, (1, s sigma) with one) and the outcome bit
+// masks (atomic OR into words cleared beforehand) for the frame update.
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_meas(MpsDev m, const uint64_t *snap_sign, const c64 *ops, const c64 *eops,
+                                             MeasStep a, const double *u, const uint8_t *forced, uint8_t *out,
+                                             double *prob, uint64_t *negmask, uint64_t *mmask) {
+  extern __shared__ __align__(16) char lds[];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  __shared__ c64 cf[2];
+  __shared__ int sweeps;
+  int *b = bnd(m, s);
+  const int l = a.l, r = a.r;
+  int c = a.center_in;
+  PhaseClock clk(false);
+  while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
+  while (c > l) { blk_move_left<T, NT>(m, s, c, lds); --c; }
+  // centre norm and <phi|P'|phi>
+  double part = 0;
+  {
+    const int cnt = b[l] * 2 * b[l + 1];
+    const cplx<T> *A = slot<T>(m, l, s);
+    for (int e = tid; e < cnt; e += NT) part += norm2(cvt<double>(A[e]));
+  }
+  const double N = bsum<NT>(part);
+  c64 *E = m.E + (size_t)s * m.E_cap, *F = m.F + (size_t)s * m.F_cap;
+  {
+    const int d = b[l];
+    for (int e = tid; e < d * d; e += NT) E[e] = mk<double>((e / d) == (e % d) ? 1.0 : 0.0, 0);
+    __syncthreads();
+  }
+  for (int j = l; j <= r; ++j) {
+    const int dl = b[j], dr = b[j + 1];
+    const cplx<T> *A = slot<T>(m, j, s);
+    blk_gemm<double, T, double, double, NT>(dl, 2 * dr, dl, E, dl, 0, A, 2 * dr, 0, F, 2 * dr, lds);
+    const c64 *o = eops + (size_t)(j - l) * 4;
+    for (int e = tid; e < dl * dr; e += NT) {
+      const int x = e / dr, y = e % dr;
+      const c64 f0 = F[(size_t)(x * 2 + 0) * dr + y], f1 = F[(size_t)(x * 2 + 1) * dr + y];
+      F[(size_t)(x * 2 + 0) * dr + y] = o[0] * f0 + o[1] * f1;
+      F[(size_t)(x * 2 + 1) * dr + y] = o[2] * f0 + o[3] * f1;
     }
     __syncthreads();
-    clk.lap(m, 2);
-    c64 *Es = m.Es + (size_t)s * m.Es_cap, *Fs = m.Fs + (size_t)s * m.Fs_cap;
-    const int eb2 = m.ebond * m.ebond;
-    if (env) {
-      // E_l = B_l^H B_l (B_l as 2 w[l] x w[l+1]); then E_j through site r-1
-      {
-        const int D = w[l + 1], K = 2 * w[l];
-        blk_gemm<T, T, double, double, NT>(D, D, K, wslot<T>(m, l, s), D, 1, wslot<T>(m, l, s), D, 0, Es, D, lds);
-        if (tid == 0) {
-          add_work(m, K_LAYER, gemm_flops(D, D, K), (double)sizeof(cplx<T>) * K * D + 16.0 * D * D);
-          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(D, D, K));
-        }
-      }
-      for (int j = l + 1; j < r; ++j) {
-        const int Dl = w[j], Dr = w[j + 1];
-        c64 *Ep = Es + (size_t)(j - 1 - l) * eb2, *Ej = Es + (size_t)(j - l) * eb2;
-        blk_gemm<double, T, double, double, NT>(Dl, 2 * Dr, Dl, Ep, Dl, 0, wslot<T>(m, j, s), 2 * Dr, 0, Fs, 2 * Dr, lds);
-        blk_gemm<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, Fs, Dr, 0, Ej, Dr, lds);
-        if (tid == 0) {
-          const double f = gemm_flops(Dl, 2 * Dr, Dl) + gemm_flops(Dr, Dr, 2 * Dl);
-          add_work(m, K_LAYER, f, (double)sizeof(cplx<T>) * 2 * Dl * Dr + 16.0 * (Dl * Dl + 2.0 * Dl * Dr + Dr * Dr));
-          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f);
-        }
-      }
-      blk_copy<T, NT>(scr<T>(m.T, m.T_cap, s), wslot<T>(m, r, s), 2 * w[r] * w[r + 1]);
-      clk.lap(m, 3);
-    }
-    // left-to-right QR sweep: B_j = Q R, Q -> workspace slot j, R B_{j+1} -> T
-    for (int j = l; j < r && !env; ++j) {
-      const int rows = 2 * w[j], cols = w[j + 1], N = 2 * w[j + 2];
-      const int p = rows < cols ? rows : cols;
-      cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
-      blk_qr<T, NT>(m, s, rows, cols, X, wslot<T>(m, j, s), 0, R, lds);
-      clk.lap(m, 3);
-      blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, wslot<T>(m, j + 1, s), N, 0, X, N, lds);
-      clk.lap(m, 4);
-      if (tid == 0) {
-        w[j + 1] = p;
-        add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
-        add_work(m, K_LAYER, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
-      }
-      __syncthreads();
-    }
-    // right-to-left truncation sweep
-    for (int j = r; j > l; --j) {
-      const int Lx = w[j], nn = 2 * w[j + 1];
-      cplx<T> *X = scr<T>(m.T, m.T_cap, s);
-      c64 *Gg = m.G + s * m.G_cap;
-      if (env) {                              // rho = X^H (E_{j-1} X)
-        const c64 *Ep = Es + (size_t)(j - 1 - l) * eb2;
-        blk_gemm<double, T, double, double, NT>(Lx, nn, Lx, Ep, Lx, 0, X, nn, 0, Fs, nn, lds);
-        blk_gemm<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, Fs, nn, 0, Gg, nn, lds);
-        if (tid == 0) {
-          add_work(m, K_LAYER, gemm_flops(Lx, nn, Lx), 16.0 * (Lx * Lx + Lx * nn));
-          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(Lx, nn, Lx));
-        }
-      } else {
-        blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
-      }
-      clk.lap(m, 5);
-      {
-        const Fallback f = fallback(m, s);
-        const bool lp = nn <= kLdsPairs;
-        int *pos = lp ? reinterpret_cast<int *>(lds + kPos) : f.pos;
-        int *pp = lp ? reinterpret_cast<int *>(lds + kPp) : f.pp;
-        int *pq = lp ? reinterpret_cast<int *>(lds + kPq) : f.pq;
-        double *pc = lp ? reinterpret_cast<double *>(lds + kPc) : f.pc;
-        double *ps = lp ? reinterpret_cast<double *>(lds + kPs) : f.ps;
-        c64 *pe = lp ? reinterpret_cast<c64 *>(lds + kPe) : f.pe;
-        c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
-        int ldw = nn;
-        if (nn <= kLdsEigN) {                 // rotate in LDS (rows padded), write the sorted vectors back
-          c64 *Gl = reinterpret_cast<c64 *>(lds);
-          ldw = nn + 1;
-          for (int e = tid; e < nn * nn; e += NT) {
-            const int r0 = e / nn, c0 = e - r0 * nn;
-            Gl[r0 * ldw + c0] = Gg[e];
-          }
-          __syncthreads();
-          Gw = Gl;
-          Vw = Gl + kLdsEigN * (kLdsEigN + 1);
-        }
-        jacobi_block<NT>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, &sweeps,
-                         sizeof(T) == 8 ? 1e-18 : 1e-16, sizeof(T) == 8 ? 1e-15 : 1e-13);
-        if (tid == 0) {
-          const double f64 = gemm_flops(nn, nn, Lx) + 36.0 * nn * nn * (double)nn;
-          add_work(m, K_LAYER, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
-          if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
-          if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)sweeps);
-        }
-        clk.lap(m, 6);
-      }
-      cplx<T> *Vt = scr<T>(m.Vt, m.Vt_cap, s);
-      const int k = select_body<T, NT>(m, s, j, Vt);
-      cplx<T> *Nn = scr<T>(m.N, m.N_cap, s);
-      blk_gemm<T, T, T, T, NT>(Lx, k, nn, X, nn, 0, Vt, k, 0, Nn, k, lds);
-      const int M = 2 * w[j - 1];
-      blk_gemm<T, T, T, T, NT>(M, k, Lx, wslot<T>(m, j - 1, s), Lx, 0, Nn, k, 0, X, k, lds);
-      if (tid == 0) {
-        w[j] = k;
-        add_work(m, K_LAYER, gemm_flops(Lx, k, nn) + gemm_flops(M, k, Lx),
-                 (double)sizeof(cplx<T>) * ((double)Lx * nn + (double)nn * k + 2.0 * Lx * k + (double)M * Lx + (double)M * k));
-      }
-      __syncthreads();
-    }
-    finish_body<T, NT>(m, s, l, scr<T>(m.T, m.T_cap, s));
-    clk.lap(m, 7);
-    c = l;
+    blk_gemm<T, double, double, double, NT>(dr, dr, 2 * dl, A, dr, 1, F, dr, 0, E, dr, lds);
+    if (tid == 0)
+      add_work(m, K_EXPECT, gemm_flops(dl, 2 * dr, dl) + gemm_flops(dr, dr, 2 * dl),
+               (double)sizeof(cplx<T>) * 2 * dl * dr + 16.0 * (dl * dl + 4.0 * dl * dr + dr * dr));
   }
+  double tp = 0;
+  {
+    const int d = b[r + 1];
+    for (int i = tid; i < d; i += NT) tp += E[(size_t)i * d + i].x;
+  }
+  const double tr = bsum<NT>(tp);
+  if (tid == 0) {
+    const double sg = ((snap_sign[s >> 6] >> (s & 63)) & 1ull) ? -1.0 : 1.0;
+    double p0 = (N + sg * tr) / (2 * N);
+    p0 = fmin(1.0, fmax(0.0, p0));
+    if (!(p0 == p0)) { atomicOr(m.err, STN_ERR_NUMERIC); p0 = 0.5; }
+    int mm;
+    if (forced) mm = forced[(size_t)s * a.n_meas + a.mi] ? 1 : 0;
+    else mm = u[(size_t)s * a.n_meas + a.mi] < p0 ? 0 : 1;
+    double pm = mm ? 1.0 - p0 : p0;
+    if (pm <= 0) { atomicOr(m.err, STN_ERR_ZEROPROB); pm = 1e-300; }
+    m.logp[s] += log(pm);
+    m.pm[s] = pm;
+    m.p0[s] = p0;
+    if (out) out[(size_t)s * a.n_meas + a.mi] = (uint8_t)mm;
+    if (prob) prob[(size_t)s * a.n_meas + a.mi] = pm;
+    const double ss = mm ? -1.0 : 1.0;
+    if (ss * sg < 0) atomicOr((unsigned long long *)&negmask[s >> 6], 1ull << (s & 63));
+    if (mm) atomicOr((unsigned long long *)&mmask[s >> 6], 1ull << (s & 63));
+    if (a.pivot < 0) { cf[0] = mk<double>(0.5, 0); cf[1] = mk<double>(0.5 * ss * sg, 0); }
+    else { cf[0] = mk<double>(1, 0); cf[1] = mk<double>(ss * sg, 0); }
+  }
+  __syncthreads();
+  const SiteOps so{ops, nullptr, nullptr, l};
+  shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], false, c, lds, clk, &sweeps);
+}
+
+__global__ void k_clear_words(uint64_t *a, uint64_t *b, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) { a[i] = 0; b[i] = 0; }
 }
 
 template <typename T, int NT>
@@ -360,6 +496,25 @@ size_t layer_fallback_bytes(int chi) {
          2 * (P / 2 + 1) * sizeof(double) + (P + 2) * sizeof(int) + 2 * (P / 2 + 1) * sizeof(int) + 64;
 }
 
+template <typename T, int NT>
+void launch_meas(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *d_ops, const c64 *d_eops,
+                 const MeasStep &a, const double *d_u, const uint8_t *d_forced, uint8_t *d_out, double *d_prob,
+                 uint64_t *d_negmask, uint64_t *d_mmask, hipStream_t st) {
+  KLAUNCH(K_LAYER, (k_meas<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT), st, m, d_snap_sign, d_ops, d_eops, a, d_u,
+          d_forced, d_out, d_prob, d_negmask, d_mmask);
+}
+
+template <typename T>
+void mps_measure_fused(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *d_ops, const c64 *d_eops,
+                       const MeasStep &a, const double *d_u, const uint8_t *d_forced, uint8_t *d_out,
+                       double *d_prob, uint64_t *d_negmask, uint64_t *d_mmask, int nt, hipStream_t st) {
+  const int SW = (m.S + 63) / 64;
+  KLAUNCH(K_TABLEAU, k_clear_words, dim3(1), dim3(64), 0, st, d_negmask, d_mmask, SW);
+  if (nt == 64) launch_meas<T, 64>(m, d_snap_sign, d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, st);
+  else if (nt == 128) launch_meas<T, 128>(m, d_snap_sign, d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, st);
+  else launch_meas<T, 256>(m, d_snap_sign, d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, st);
+}
+
 template <typename T>
 void mps_rot_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
                    const double *d_theta, int64_t stride, const RotLayer &L, int nt, hipStream_t st) {
@@ -371,9 +526,10 @@ void mps_rot_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_p
 template <typename T>
 hipError_t layer_prepare() {
   hipError_t e = hipSuccess;
-  const void *fs[3] = {(const void *)k_layer<T, 64>, (const void *)k_layer<T, 128>, (const void *)k_layer<T, 256>};
-  const int nts[3] = {64, 128, 256};
-  for (int i = 0; i < 3; ++i) {
+  const void *fs[6] = {(const void *)k_layer<T, 64>, (const void *)k_layer<T, 128>, (const void *)k_layer<T, 256>,
+                       (const void *)k_meas<T, 64>, (const void *)k_meas<T, 128>, (const void *)k_meas<T, 256>};
+  const int nts[6] = {64, 128, 256, 64, 128, 256};
+  for (int i = 0; i < 6; ++i) {
     hipError_t e2 = hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(nts[i]));
     if (e == hipSuccess) e = e2;
   }
@@ -384,5 +540,11 @@ template void mps_rot_layer<float>(const MpsDev &, const uint64_t *, const uint6
                                    const double *, int64_t, const RotLayer &, int, hipStream_t);
 template void mps_rot_layer<double>(const MpsDev &, const uint64_t *, const uint64_t *, int, int,
                                     const double *, int64_t, const RotLayer &, int, hipStream_t);
+template void mps_measure_fused<float>(const MpsDev &, const uint64_t *, const c64 *, const c64 *, const MeasStep &,
+                                       const double *, const uint8_t *, uint8_t *, double *, uint64_t *, uint64_t *,
+                                       int, hipStream_t);
+template void mps_measure_fused<double>(const MpsDev &, const uint64_t *, const c64 *, const c64 *, const MeasStep &,
+                                        const double *, const uint8_t *, uint8_t *, double *, uint64_t *, uint64_t *,
+                                        int, hipStream_t);
 template hipError_t layer_prepare<float>();
 template hipError_t layer_prepare<double>();

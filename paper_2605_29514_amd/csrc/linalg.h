@@ -441,6 +441,14 @@ __device__ void jacobi_block(int nn, c64 *G, int ld, c64 *V, double *ev, c64 *Vo
   __syncthreads();
 }
 
+// Stopping rule of the Jacobi solve per storage precision.  FP64 states
+// converge the off-diagonal to 1e-15 relative (floor 1e-18 of the trace).
+// FP32 states store the kept vectors in FP32 (relative rounding 6e-8), so
+// 1e-10 relative with a 1e-15 floor (the rounding level of a Gram of FP32
+// data) already leaves the eigenvectors far more accurate than stored.
+template <typename T> __device__ inline double jac_abs() { return sizeof(T) == 8 ? 1e-18 : 1e-15; }
+template <typename T> __device__ inline double jac_rel() { return sizeof(T) == 8 ? 1e-15 : 1e-10; }
+
 // ------------------------------------------------------------ truncation
 // Keep k' = min(chi_max, #{lambda_i > eps sum lambda}, 2^min(j, n-j)) largest
 // (at least 1); the discarded weight updates the fidelity; Vt = V[:, :k']
@@ -461,9 +469,12 @@ __device__ int select_body(const MpsDev &m, int s, int j, cplx<T> *Vt) {
   if (threadIdx.x == 0) {
     int k = cnt < m.chi ? cnt : m.chi;
     const int e = j < m.n - j ? j : m.n - j;           // physical bound 2^min(j, n-j)
-    if (e < 30 && k > (1 << e)) k = 1 << e;
+    const bool phys = e < 30 && k > (1 << e);
+    if (phys) k = 1 << e;
     if (k < 1) k = 1;
-    if (k < cnt) m.trunc[s] = 1;                       // weight above the cut was dropped
+    // chi_max dropped values above the cut (the physical bound only ever
+    // clips rounding noise, so it does not count)
+    if (cnt > m.chi && !phys) m.trunc[s] = 1;
     double disc = 0;
     for (int i = k; i < nn; ++i) disc += fmax(ev[i], 0.0);
     const double wgt = tot > 0 ? disc / tot : 0.0;

@@ -211,7 +211,7 @@ __global__ void k_eig(MpsDev m, int j) {
   __shared__ int sweeps;
   jacobi_block<TB>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg,
                m.err, pos, pc, ps, pe, pp, pq, &sweeps,
-               sizeof(T) == 8 ? 1e-18 : 1e-16, sizeof(T) == 8 ? 1e-15 : 1e-13);
+               jac_abs<T>(), jac_rel<T>());
   // algorithmic work: a Hermitian eigendecomposition with vectors, ~9 n^3 real
   // flops (x4 complex); bytes: read G, write eigenvalues and vectors.
   if (threadIdx.x == 0) add_work(m, K_EIGEN, 36.0 * nn * nn * (double)nn, 16.0 * 2 * nn * nn + 8.0 * nn);

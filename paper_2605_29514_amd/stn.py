@@ -44,7 +44,7 @@ EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn
            "stn_set_site", "stn_set_center", "stn_set_layer_mode", "stn_set_layer_threads", "stn_reset",
            "stn_tape_bytes", "stn_tape_begin", "stn_tape_end", "stn_adjoint_bytes", "stn_adjoint_init",
            "stn_adjoint_zero", "stn_backward", "stn_checkpoint_bytes", "stn_checkpoint_save",
-           "stn_checkpoint_load", "stn_profile_phases"]
+           "stn_checkpoint_load", "stn_profile_phases", "stn_adjoint_truncated"]
 K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect", "layer"]
 
 
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH):
     lib.stn_adjoint_zero.argtypes = [vp]
     lib.stn_backward.restype = i32
     lib.stn_backward.argtypes = [vp, vp, i64]
+    lib.stn_adjoint_truncated.restype = i32
+    lib.stn_adjoint_truncated.argtypes = [vp, vp]
     lib.stn_profile_phases.restype = i32
     lib.stn_profile_phases.argtypes = [vp, vp]
     lib.stn_checkpoint_bytes.restype = ctypes.c_size_t
@@ -271,6 +273,12 @@ class Simulator:
 
     def adjoint_zero(self):
         self._check(self.lib.stn_adjoint_zero(self.ctx))
+
+    def adjoint_truncated(self) -> np.ndarray:
+        """Per shot: did the adjoint state's bond cap drop weight?"""
+        out = np.zeros(self.S, np.int32)
+        self._check(self.lib.stn_adjoint_truncated(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
+        return out.astype(bool)
 
     def backward(self, grad, col: int = 0):
         """grad: float64 device tensor [S, R]; the tape's rotations go to

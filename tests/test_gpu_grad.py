@@ -57,6 +57,7 @@ def check(A, circ, chi, prec, segments=None):
     run = A.GradientRun(circ, chi, recs, prec, EPS[prec], segments=segments)
     lp = run.forward().cpu().numpy()
     g = run.backward().cpu().numpy()
+    assert not run.adjoint_truncated.any(), "adjoint bond cap reached"
     used = 0
     for s, t in enumerate(tapes):
         if sens[s] > MAX_SENS[prec]:
@@ -101,6 +102,16 @@ def test_checkpoint_stretches_agree(A):
     gb = b.backward().cpu().numpy()
     assert len(a.segments) > 2
     assert np.max(np.abs(ga - gb)) <= 1e-9 * max(1.0, np.abs(gb).max())
+
+
+def test_adjoint_cap_is_reported(A):
+    """A cap equal to the forward's is too small for this adjoint: the flag says so."""
+    circ = W.memory_circuit(3, 2, 2, seed=5, theta_nn=0.1, p=0.02, per_layer_params=True)
+    _, recs, _ = oracle_case(circ, 4, "fp64")
+    run = A.GradientRun(circ, 4, recs, "fp64", EPS["fp64"], chi_adj=4)
+    run.forward()
+    run.backward()
+    assert run.adjoint_truncated.any()
 
 
 def test_autograd_function(A):
