@@ -57,14 +57,23 @@ CLASS_BOUND = {
 }
 
 
+def kernel_source_hash():
+    """sha256 (first 16 hex) of the kernel sources, in a fixed order; a
+    stored traffic figure counts only while it matches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("common.h", "linalg.h", "mps.hip", "layer.hip"):
+        with open(os.path.join(ROOT, "paper_2605_29514_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel_class):
     """HBM bytes per launch of a kernel class from the committed rocprofv3 PMC
     summary (profiles/traffic_*.json), or None when no summary matches the
     class or the kernel source changed since the counters were taken."""
     import glob
-    import hashlib
-    src = os.path.join(ROOT, "paper_2605_29514_amd", "csrc", "mps.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_hash()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
         with open(path) as f:
             t = json.load(f)
@@ -92,44 +101,48 @@ def rotations_in(circ_ops, lo, hi):
 
 # ----------------------------------------------------------------- CPU leg
 def _oracle_worker(args):
-    name, shot, shots_total, warm_lo, warm_hi, t_lo, t_hi, budget, chi, eps = args
+    """Runs shots of the workload on the FP64 oracle, one after the other,
+    timing only the rotations of the timed rounds, until the time budget is
+    used; returns (rotations timed, seconds timed)."""
+    name, shots, shots_total, t_lo, t_hi, budget, chi, eps = args
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import stn as ostn
     from paper_2605_29514_amd import workload
     circ, _ = workload.make_config(name, n_shots=shots_total)
-    st = ostn.Shot(circ.n, chi, eps)
-    done = 0
-    t0 = None
-    for oi, op in enumerate(circ.ops):
-        if oi == t_lo:
-            t0 = time.perf_counter()
-        if t0 is not None and (oi >= t_hi or time.perf_counter() - t0 > budget):
+    done, busy = 0, 0.0
+    for shot in shots:
+        if busy > budget:
             break
-        k = op["op"]
-        if k == "gates":
-            for g in op["gates"]:
-                st.gate(g[0], [g[1], g[2]])
-        elif k == "noise":
-            st.pauli_noise(op["x"][shot], op["z"][shot])
-        elif k == "rotate":
-            for ri, qs in enumerate(op["paulis"]):
-                st.rotate([int(q) for q in qs], float(op["theta"][shot, ri]))
-                if t0 is not None:
-                    done += 1
-                    if time.perf_counter() - t0 > budget:
-                        break
-        elif k == "measure":
-            for mj, q in enumerate(op["qubits"]):
-                st.measure(int(q), float(op["u"][shot, mj]), None, bool(op["reset"]))
-    el = time.perf_counter() - t0 if t0 is not None else 0.0
-    return done, el
+        st = ostn.Shot(circ.n, chi, eps)
+        for oi, op in enumerate(circ.ops[:t_hi]):
+            timed = oi >= t_lo
+            k = op["op"]
+            if k == "gates":
+                for g in op["gates"]:
+                    st.gate(g[0], [g[1], g[2]])
+            elif k == "noise":
+                st.pauli_noise(op["x"][shot], op["z"][shot])
+            elif k == "rotate":
+                for ri, qs in enumerate(op["paulis"]):
+                    t0 = time.perf_counter()
+                    st.rotate([int(q) for q in qs], float(op["theta"][shot, ri]))
+                    if timed:
+                        busy += time.perf_counter() - t0
+                        done += 1
+            elif k == "measure":
+                for mj, q in enumerate(op["qubits"]):
+                    st.measure(int(q), float(op["u"][shot, mj]), None, bool(op["reset"]))
+    return done, busy
 
 
 def cpu_baseline(name, circ, ops_bounds, t_lo_round, t_hi_round, chi, eps, budget, cores):
-    """Oracle rotations/s over the same rounds, one shot per core (BLAS 1 thread)."""
-    # map prepared-op rounds to circuit-op indices (prepared ops mirror circuit ops 1:1)
+    """Oracle rotations/s over the same rounds: `cores` worker processes (BLAS
+    1 thread each) take shots 0, 1, 2, ... round-robin and time the
+    rotations of the timed rounds until each has spent `budget` seconds."""
+    # prepared ops mirror the circuit ops one to one
     t_lo, t_hi = ops_bounds[t_lo_round][0], ops_bounds[t_hi_round - 1][1]
-    args = [(name, s, circ.n_shots, 0, t_lo, t_lo, t_hi, budget, chi, eps) for s in range(cores)]
+    per = [list(range(w, circ.n_shots, cores)) for w in range(cores)]
+    args = [(name, per[w], circ.n_shots, t_lo, t_hi, budget, chi, eps) for w in range(cores)]
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -139,9 +152,9 @@ def cpu_baseline(name, circ, ops_bounds, t_lo_round, t_hi_round, chi, eps, budge
     busy = max(r[1] for r in res)
     return {"value": done / busy if busy > 0 else 0.0, "unit": "rotations/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{cores} shots (one per core, FP64 numpy, BLAS 1 thread) replayed to the timed "
-                      f"rounds, then up to {budget:.0f} s of rotations each; {done} rotations in {busy:.1f} s "
-                      f"(wall incl. replay {wall:.1f} s)"}
+            "sample": f"{cores} worker processes (FP64 numpy oracle, BLAS 1 thread each) taking shots "
+                      f"round-robin, each timing the rotations of the timed rounds until {budget:.0f} s were "
+                      f"spent; {done} rotations, slowest worker {busy:.1f} s (wall incl. replays {wall:.1f} s)"}
 
 
 # ----------------------------------------------------------------- main

@@ -94,7 +94,7 @@ __device__ void blk_qr(const MpsDev &m, int s, int rows, int cols, cplx<T> *A, c
 
 // Centre move c -> c+1 (QR of A_c, R into A_{c+1}).
 template <typename T, int NT>
-__device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds) {
+__device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds, int cls) {
   int *b = bnd(m, s);
   const int rows = 2 * b[c], cols = b[c + 1], N = 2 * b[c + 2];
   const int p = rows < cols ? rows : cols;
@@ -104,8 +104,8 @@ __device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds) {
   blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, slot<T>(m, c + 1, s), N, 0, X, N, lds);
   if (threadIdx.x == 0) {
     b[c + 1] = p;
-    add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
-    add_work(m, K_LAYER, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
+    add_work(m, cls, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+    add_work(m, cls, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
   }
   __syncthreads();
   blk_copy<T, NT>(slot<T>(m, c + 1, s), X, p * N);
@@ -113,7 +113,7 @@ __device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds) {
 
 // Centre move c -> c-1 (LQ of A_c via the QR of A_c^H, L into A_{c-1}).
 template <typename T, int NT>
-__device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds) {
+__device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds, int cls) {
   int *b = bnd(m, s);
   const int dl = b[c], dr = b[c + 1], M = 2 * b[c - 1];
   const int rows = 2 * dr, cols = dl, p = rows < cols ? rows : cols;
@@ -128,8 +128,8 @@ __device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds) {
   blk_gemm<T, T, T, T, NT>(M, p, cols, slot<T>(m, c - 1, s), cols, 0, R, cols, 1, X, p, lds);
   if (threadIdx.x == 0) {
     b[c] = p;
-    add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
-    add_work(m, K_LAYER, gemm_flops(M, p, cols), (double)sizeof(cplx<T>) * ((double)M * cols + (double)cols * p + (double)M * p));
+    add_work(m, cls, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+    add_work(m, cls, gemm_flops(M, p, cols), (double)sizeof(cplx<T>) * ((double)M * cols + (double)cols * p + (double)M * p));
   }
   __syncthreads();
   blk_copy<T, NT>(slot<T>(m, c - 1, s), X, M * p);
@@ -177,13 +177,14 @@ struct SiteOps {
 // and renormalises.
 template <typename T, int NT>
 __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &so, c64 ca, c64 cb, bool unitary,
-                          int &c, char *lds, PhaseClock &clk, int *sweeps) {
+                          int &c, char *lds, PhaseClock &clk, int *sweeps, int cls) {
+  const bool f64c = m.prof && cls == K_LAYER;   // FP64 share is tracked for the layer class
   const int tid = threadIdx.x;
   int *b = bnd(m, s), *w = wbd(m, s);
   if (l == r) {
     if (!unitary) {
-      while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
-      while (c > l) { blk_move_left<T, NT>(m, s, c, lds); --c; }
+      while (c < l) { blk_move_right<T, NT>(m, s, c, lds, cls); ++c; }
+      while (c > l) { blk_move_left<T, NT>(m, s, c, lds, cls); --c; }
     }
     c64 o1[4], o2[4];
     so.get(l, o1, o2);
@@ -214,8 +215,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     return;
   }
   clk.lap(m, 0);
-  while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
-  while (c > r) { blk_move_left<T, NT>(m, s, c, lds); --c; }
+  while (c < l) { blk_move_right<T, NT>(m, s, c, lds, cls); ++c; }
+  while (c > r) { blk_move_left<T, NT>(m, s, c, lds, cls); --c; }
   clk.lap(m, 1);
   // Environment path: when every doubled bond of the span fits the shot's
   // Gram store, the left-to-right sweep forms the left-environment Grams
@@ -267,8 +268,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
       const int D = w[l + 1], K = 2 * w[l];
       blk_gemm<T, T, double, double, NT>(D, D, K, wslot<T>(m, l, s), D, 1, wslot<T>(m, l, s), D, 0, Es, D, lds);
       if (tid == 0) {
-        add_work(m, K_LAYER, gemm_flops(D, D, K), (double)sizeof(cplx<T>) * K * D + 16.0 * D * D);
-        if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(D, D, K));
+        add_work(m, cls, gemm_flops(D, D, K), (double)sizeof(cplx<T>) * K * D + 16.0 * D * D);
+        if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(D, D, K));
       }
     }
     for (int j = l + 1; j < r; ++j) {
@@ -278,8 +279,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
       blk_gemm<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, Fs, Dr, 0, Ej, Dr, lds);
       if (tid == 0) {
         const double f = gemm_flops(Dl, 2 * Dr, Dl) + gemm_flops(Dr, Dr, 2 * Dl);
-        add_work(m, K_LAYER, f, (double)sizeof(cplx<T>) * 2 * Dl * Dr + 16.0 * (Dl * Dl + 2.0 * Dl * Dr + Dr * Dr));
-        if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f);
+        add_work(m, cls, f, (double)sizeof(cplx<T>) * 2 * Dl * Dr + 16.0 * (Dl * Dl + 2.0 * Dl * Dr + Dr * Dr));
+        if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], f);
       }
     }
     blk_copy<T, NT>(scr<T>(m.T, m.T_cap, s), wslot<T>(m, r, s), 2 * w[r] * w[r + 1]);
@@ -296,8 +297,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     clk.lap(m, 4);
     if (tid == 0) {
       w[j + 1] = p;
-      add_work(m, K_LAYER, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
-      add_work(m, K_LAYER, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
+      add_work(m, cls, qr_flops(rows, cols), (double)sizeof(cplx<T>) * (2.0 * rows * cols + (double)rows * p + (double)p * cols));
+      add_work(m, cls, gemm_flops(p, N, cols), (double)sizeof(cplx<T>) * ((double)p * cols + (double)cols * N + (double)p * N));
     }
     __syncthreads();
   }
@@ -311,8 +312,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
       blk_gemm<double, T, double, double, NT>(Lx, nn, Lx, Ep, Lx, 0, X, nn, 0, Fs, nn, lds);
       blk_gemm<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, Fs, nn, 0, Gg, nn, lds);
       if (tid == 0) {
-        add_work(m, K_LAYER, gemm_flops(Lx, nn, Lx), 16.0 * (Lx * Lx + Lx * nn));
-        if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(Lx, nn, Lx));
+        add_work(m, cls, gemm_flops(Lx, nn, Lx), 16.0 * (Lx * Lx + Lx * nn));
+        if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(Lx, nn, Lx));
       }
     } else {
       blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
@@ -344,8 +345,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
                        jac_abs<T>(), jac_rel<T>());
       if (tid == 0) {
         const double f64 = gemm_flops(nn, nn, Lx) + 36.0 * nn * nn * (double)nn;
-        add_work(m, K_LAYER, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
-        if (m.prof) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
+        add_work(m, cls, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
+        if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
         if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)*sweeps);
       }
       clk.lap(m, 6);
@@ -358,7 +359,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     blk_gemm<T, T, T, T, NT>(M, k, Lx, wslot<T>(m, j - 1, s), Lx, 0, Nn, k, 0, X, k, lds);
     if (tid == 0) {
       w[j] = k;
-      add_work(m, K_LAYER, gemm_flops(Lx, k, nn) + gemm_flops(M, k, Lx),
+      add_work(m, cls, gemm_flops(Lx, k, nn) + gemm_flops(M, k, Lx),
                (double)sizeof(cplx<T>) * ((double)Lx * nn + (double)nn * k + 2.0 * Lx * k + (double)M * Lx + (double)M * k));
     }
     __syncthreads();
@@ -390,7 +391,7 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
     }
     __syncthreads();
     const SiteOps so{nullptr, bx, bz, l};
-    shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], true, c, lds, clk, &sweeps);
+    shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], true, c, lds, clk, &sweeps, K_LAYER);
   }
 }
 
@@ -412,8 +413,8 @@ __global__ void __launch_bounds__(NT) k_meas(MpsDev m, const uint64_t *snap_sign
   const int l = a.l, r = a.r;
   int c = a.center_in;
   PhaseClock clk(false);
-  while (c < l) { blk_move_right<T, NT>(m, s, c, lds); ++c; }
-  while (c > l) { blk_move_left<T, NT>(m, s, c, lds); --c; }
+  while (c < l) { blk_move_right<T, NT>(m, s, c, lds, K_EXPECT); ++c; }
+  while (c > l) { blk_move_left<T, NT>(m, s, c, lds, K_EXPECT); --c; }
   // centre norm and <phi|P'|phi>
   double part = 0;
   {
@@ -474,7 +475,7 @@ __global__ void __launch_bounds__(NT) k_meas(MpsDev m, const uint64_t *snap_sign
   }
   __syncthreads();
   const SiteOps so{ops, nullptr, nullptr, l};
-  shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], false, c, lds, clk, &sweeps);
+  shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], false, c, lds, clk, &sweeps, K_EXPECT);
 }
 
 __global__ void k_clear_words(uint64_t *a, uint64_t *b, int n) {
@@ -500,7 +501,7 @@ template <typename T, int NT>
 void launch_meas(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *d_ops, const c64 *d_eops,
                  const MeasStep &a, const double *d_u, const uint8_t *d_forced, uint8_t *d_out, double *d_prob,
                  uint64_t *d_negmask, uint64_t *d_mmask, hipStream_t st) {
-  KLAUNCH(K_LAYER, (k_meas<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT), st, m, d_snap_sign, d_ops, d_eops, a, d_u,
+  KLAUNCH(K_EXPECT, (k_meas<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT), st, m, d_snap_sign, d_ops, d_eops, a, d_u,
           d_forced, d_out, d_prob, d_negmask, d_mmask);
 }
 
