@@ -279,7 +279,7 @@ def main():
         cpu = cpu_baseline(args.config, circ, rounds, W, W + K, chi, 1e-16 if prec == "fp64" else 1e-14,
                            args.cpu_seconds, cores)
     out = {
-        "metric": "crosstalk rotations/sec (shots x gates) at d=5, chi=256",
+        "metric": f"crosstalk rotations/sec (shots x gates) at d={cfg['d']}, chi={chi}",
         "value": value, "unit": "rotations/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 contractions + f64 gram/eigen/norms" if prec == "fp32" else "c128",

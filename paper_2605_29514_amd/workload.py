@@ -372,6 +372,11 @@ CONFIGS = {
     "d5_nnn_chi256": dict(d=5, rounds=5, n_shots=1024, theta_law="per_coupling", nnn=True,
                           theta_range=(0.02, 0.10), p=1e-3, chi_max=256,
                           precision="fp32", seed=21),
+    # the d=5 workload at the bond cap the paper uses for all its results
+    # (chi 32, Sec. IV.B): chi binds from the second round on
+    "d5_nnn_chi32": dict(d=5, rounds=5, n_shots=1024, theta_law="per_coupling", nnn=True,
+                         theta_range=(0.02, 0.10), p=1e-3, chi_max=32,
+                         precision="fp32", seed=21),
     # d=7, 7 rounds, per-shot theta in [0.01, 0.08], NNN at half, chi 512
     "d7_nnn_chi512": dict(d=7, rounds=7, n_shots=4096, theta_law="per_shot", nnn=True,
                           theta_range=(0.01, 0.08), p=0.0, chi_max=512,
