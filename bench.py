@@ -229,10 +229,18 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(sim.stream)
+    round_ev = []
     for r in range(W, W + K):
         stn.run_prepared(sim, ops, *rounds[r])
-        print(f"# timed round {r + 1} enqueued at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+        round_ev.append(torch.cuda.Event())
+        round_ev[-1].record(sim.stream)
     ev1.record(sim.stream)
+    # progress: poll the per-round events (host side only; the GPU timeline
+    # is what ev0 / ev1 measure)
+    for i, e in enumerate(round_ev):
+        while not e.query():
+            time.sleep(0.05)
+        print(f"# timed round {W + i + 1} done at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
@@ -276,7 +284,7 @@ def main():
     if not args.no_cpu:
         cores = min(os.cpu_count() or 1, 16)
         print(f"# cpu baseline on {cores} cores", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.config, circ, rounds, W, W + K, chi, 1e-16 if prec == "fp64" else 1e-14,
+        cpu = cpu_baseline(args.config, circ, rounds, W, W + K, chi, eps,
                            args.cpu_seconds, cores)
     out = {
         "metric": f"crosstalk rotations/sec (shots x gates) at d={cfg['d']}, chi={chi}",

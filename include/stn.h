@@ -62,7 +62,11 @@ typedef struct {
     int n_shots;         /* independent shots simulated together, >= 1 */
     int chi_max;         /* bond-dimension cap (Sec. IV.B), 1..512 */
     int precision;       /* STN_FP64 or STN_FP32 */
-    double eps_cut;      /* drop Schmidt values with lambda^2 <= eps_cut * sum lambda^2 */
+    double eps_cut;      /* drop Schmidt values with lambda^2 <= eps_cut * sum lambda^2
+                            (Eq. 8).  The squared values come from an FP64 Gram
+                            eigen-solve, whose absolute error is a few FP64 epsilons
+                            times sum lambda^2: cuts below ~1e-14 let rounding
+                            decide the kept count. */
     void *stream;        /* hipStream_t, or NULL for the default stream */
 } stn_config;
 
@@ -200,7 +204,9 @@ stn_status stn_tape_end(stn_ctx *ctx, int *n_rotations);
 size_t stn_adjoint_bytes(const stn_ctx *ctx, int chi_adj);
 
 /* Places the adjoint state in dev_buf (caller-owned, 256-byte aligned, at
- * least stn_adjoint_bytes) and sets it to zero.  Synchronises. */
+ * least stn_adjoint_bytes) and sets it to zero.  Synchronises.  The adjoint
+ * state is compressed with a relative cut of eps_cut / 100: the gradient is
+ * linear in it, so a dropped squared value lambda costs ~sqrt(lambda). */
 stn_status stn_adjoint_init(stn_ctx *ctx, void *dev_buf, size_t bytes, int chi_adj);
 
 /* Sets the adjoint state to zero (start of a backward pass) and clears the

@@ -84,6 +84,14 @@ class MPS:
         # largest values but leaves ties at the cut open; a large value means the
         # kept subspace is ill-conditioned.
         self.max_cut_sensitivity = 0.0
+        # margin of the chi decision at the relative cut: where more than
+        # chi_max values exist, chi_max drops weight above the cut iff
+        # s_chi^2 > eps sum s^2 (0-based index chi_max); the margin is
+        # max(r, 1/r) with r the ratio of the two sides, its smallest value
+        # over the run is kept.  A value near 1 means the decision (and with it
+        # whether a step counts as truncated) is set by rounding: values near
+        # eps sum s^2 are at the noise floor of any Gram-based eigen-solve.
+        self.min_flag_margin = float("inf")
 
     # ------------------------------------------------------------------ basics
     def bonds(self):
@@ -199,6 +207,9 @@ class MPS:
             u, s, vh = svd(t.reshape(dl, 2 * dr))
             k = keep_count(s, self.chi_max, self.eps_cut)
             tot = float(np.sum(s.astype(np.float64) ** 2))
+            if len(s) > self.chi_max and self.eps_cut > 0 and tot > 0:
+                r = float(s[self.chi_max]) ** 2 / (self.eps_cut * tot)
+                self.min_flag_margin = min(self.min_flag_margin, max(r, 1.0 / r) if r > 0 else float("inf"))
             if k < len(s) and s[k] ** 2 > self.eps_cut * tot:
                 self.last_truncated = True
                 gap = float(s[k - 1] ** 2 - s[k] ** 2)

@@ -248,9 +248,12 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         const int aa = (j == l) ? a : a - (ba ? dl : 0);
         const int c2 = (j == r) ? cc : cc - (bc ? dr : 0);
         const c64 x0 = cvt<double>(A[(size_t)(aa * 2 + 0) * dr + c2]), x1 = cvt<double>(A[(size_t)(aa * 2 + 1) * dr + c2]);
-        const c64 *o = br ? o2 : o1;
-        y0 = o[0] * x0 + o[1] * x1;
-        y1 = o[2] * x0 + o[3] * x1;
+        // element-wise selects keep o1, o2 in registers (a pointer to either
+        // would put both arrays in scratch memory)
+        const c64 u0 = br ? o2[0] : o1[0], u1 = br ? o2[1] : o1[1];
+        const c64 u2 = br ? o2[2] : o1[2], u3 = br ? o2[3] : o1[3];
+        y0 = u0 * x0 + u1 * x1;
+        y1 = u2 * x0 + u3 * x1;
         if (j == l) { const c64 k = br ? cb : ca; y0 = k * y0; y1 = k * y1; }
       }
       out[(size_t)(a * 2 + 0) * Dr + cc] = cvt<T>(y0);

@@ -87,67 +87,90 @@ __device__ double bmax(double v) {
 }
 
 // ------------------------------------------------------------------ GEMM
-// Thread grid TY x TX over a GT x GT tile; each thread owns (GT/TY) x (GT/TX)
-// outputs, strided so that a row of threads reads consecutive columns.
-template <int NT> struct TileShape;
-template <> struct TileShape<64> { static constexpr int TY = 8, TX = 8; };
-template <> struct TileShape<128> { static constexpr int TY = 16, TX = 8; };
-template <> struct TileShape<256> { static constexpr int TY = 16, TX = 16; };
-
 template <typename ACC>
 struct GemmStage {
   static constexpr size_t bytes = sizeof(cplx<ACC>) * (GT * (GK + 1) + GK * (GT + 1));
 };
 
-// One GT x GT tile of C = op(A) op(B).
+// Matrix cores.  v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32 take, per
+// lane l of a wave, A[l % 16][l / 16] and B[l / 16][l % 16] of a 16x4 and a
+// 4x16 operand and accumulate a 16x16 block of which lane l holds column
+// l % 16, rows (l / 16) + 4 i (f64) or 4 (l / 16) + i (f32), i = 0..3.
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+template <typename ACC> struct Mfma;
+template <> struct Mfma<double> {
+  using V = v4d_t;
+  __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+template <> struct Mfma<float> {
+  using V = v4f_t;
+  __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+// Block tile of the matrix-core GEMM: one 16x16 block per wave, so a block
+// of NT threads covers TM x TN = (16 x 16) x (NT / 64) outputs.
+template <int NT> struct MTile;
+template <> struct MTile<64> { static constexpr int TM = 16, TN = 16; };
+template <> struct MTile<128> { static constexpr int TM = 32, TN = 16; };
+template <> struct MTile<256> { static constexpr int TM = 32, TN = 32; };
+
+// One TM x TN tile of C = op(A) op(B) on the matrix cores.
 //   opA = 0: A is M x K (lda);  opA = 1: A is K x M and op(A) = A^H.
 //   opB = 0: B is K x N (ldb);  opB = 1: B is N x K and op(B) = B^H.
+// Operands are staged through LDS in ACC precision (GK columns at a time,
+// zero-padded past M, N, K); each wave owns one 16x16 block of the tile and
+// forms it as a complex product of four real MFMA chains:
+// re += a_re b_re - a_im b_im, im += a_re b_im + a_im b_re.
 // stage: GemmStage<ACC>::bytes of LDS.
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void gemm_tile(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
                           const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, int tm,
                           int tn, void *stage) {
-  constexpr int TY = TileShape<NT>::TY, TX = TileShape<NT>::TX;
-  constexpr int RY = GT / TY, RX = GT / TX;
-  cplx<ACC> *As = reinterpret_cast<cplx<ACC> *>(stage);          // [GT][GK + 1]
-  cplx<ACC> *Bs = As + GT * (GK + 1);                              // [GK][GT + 1]
-  const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = tid / TX;
-  const int row0 = tm * GT, col0 = tn * GT;
-  cplx<ACC> acc[RY][RX];
-  for (int i = 0; i < RY; ++i)
-    for (int j = 0; j < RX; ++j) acc[i][j] = mk<ACC>(0, 0);
+  using MF = Mfma<ACC>;
+  using V = typename MF::V;
+  constexpr int TM = MTile<NT>::TM, TN = MTile<NT>::TN;
+  cplx<ACC> *As = reinterpret_cast<cplx<ACC> *>(stage);          // [TM][GK + 1]
+  cplx<ACC> *Bs = As + GT * (GK + 1);                              // [GK][TN + 1]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row0 = tm * TM, col0 = tn * TN;
+  const int sm = (wave / (TN / 16)) * 16, sn = (wave % (TN / 16)) * 16;
+  V re, im;
+  for (int i = 0; i < 4; ++i) { re[i] = 0; im[i] = 0; }
   for (int k0 = 0; k0 < K; k0 += GK) {
-    for (int e = tid; e < GT * GK; e += NT) {
+    for (int e = tid; e < TM * GK; e += NT) {
       int mi = e / GK, ki = e % GK;
       int m = row0 + mi, k = k0 + ki;
       cplx<ACC> v = mk<ACC>(0, 0);
       if (m < M && k < K) v = opA ? cj(cvt<ACC>(A[(size_t)k * lda + m])) : cvt<ACC>(A[(size_t)m * lda + k]);
       As[mi * (GK + 1) + ki] = v;
     }
-    for (int e = tid; e < GT * GK; e += NT) {
-      int ki = e / GT, ni = e % GT;
+    for (int e = tid; e < TN * GK; e += NT) {
+      int ki = e / TN, ni = e % TN;
       int n = col0 + ni, k = k0 + ki;
       cplx<ACC> v = mk<ACC>(0, 0);
       if (n < N && k < K) v = opB ? cj(cvt<ACC>(B[(size_t)n * ldb + k])) : cvt<ACC>(B[(size_t)k * ldb + n]);
-      Bs[ki * (GT + 1) + ni] = v;
+      Bs[ki * (TN + 1) + ni] = v;
     }
     __syncthreads();
     const int kend = K - k0 < GK ? K - k0 : GK;
-    for (int kk = 0; kk < kend; ++kk) {
-      cplx<ACC> a[RY], b[RX];
-      for (int i = 0; i < RY; ++i) a[i] = As[(ty + TY * i) * (GK + 1) + kk];
-      for (int j = 0; j < RX; ++j) b[j] = Bs[kk * (GT + 1) + tx + TX * j];
-      for (int i = 0; i < RY; ++i)
-        for (int j = 0; j < RX; ++j) acc[i][j] = acc[i][j] + a[i] * b[j];
+    for (int kk = 0; kk < kend; kk += 4) {
+      const cplx<ACC> a = As[(sm + (lane & 15)) * (GK + 1) + kk + (lane >> 4)];
+      const cplx<ACC> b = Bs[(kk + (lane >> 4)) * (TN + 1) + sn + (lane & 15)];
+      re = MF::mma(a.x, b.x, re);
+      re = MF::mma(-a.y, b.y, re);
+      im = MF::mma(a.x, b.y, im);
+      im = MF::mma(a.y, b.x, im);
     }
     __syncthreads();
   }
-  for (int i = 0; i < RY; ++i)
-    for (int j = 0; j < RX; ++j) {
-      int m = row0 + ty + TY * i, n = col0 + tx + TX * j;
-      if (m < M && n < N) C[(size_t)m * ldc + n] = cvt<TC>(acc[i][j]);
-    }
+  const int n = col0 + sn + (lane & 15);
+  for (int i = 0; i < 4; ++i) {
+    const int m = row0 + sm + MF::row(lane, i);
+    if (m < M && n < N) C[(size_t)m * ldc + n] = cvt<TC>(mk<ACC>(re[i], im[i]));
+  }
 }
 
 // All tiles of a product by the calling block (tiles t0, t0 + dt, ...).
@@ -155,7 +178,8 @@ template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void gemm_tiles(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
                            const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, int t0,
                            int dt, void *stage) {
-  const int ntm = (M + GT - 1) / GT, ntn = (N + GT - 1) / GT;
+  constexpr int TM = MTile<NT>::TM, TN = MTile<NT>::TN;
+  const int ntm = (M + TM - 1) / TM, ntn = (N + TN - 1) / TN;
   for (int t = t0; t < ntm * ntn; t += dt)
     gemm_tile<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, t / ntn, t % ntn, stage);
 }

@@ -19,7 +19,7 @@ STN_FP64, STN_FP32 = 0, 1
 GATE_KIND = {"H": 0, "S": 1, "SDG": 2, "X": 3, "Y": 4, "Z": 5, "CX": 6, "CY": 7, "CZ": 8}
 STATUS = {0: "STN_OK", -1: "STN_EINVAL", -2: "STN_ENOMEM", -3: "STN_EDEVICE",
           -4: "STN_EZEROPROB", -5: "STN_ENUMERIC", -6: "STN_ESTATE"}
-DEFAULT_EPS = {STN_FP64: 1e-16, STN_FP32: 1e-14}
+DEFAULT_EPS = {STN_FP64: 1e-14, STN_FP32: 1e-12}
 
 
 class STNError(RuntimeError):
@@ -53,6 +53,9 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: its HIP runtime must be the one the library binds to, or
+    # the device memory torch hands over is foreign to the library's runtime.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with python -m paper_2605_29514_amd.build")
     lib = ctypes.CDLL(path)

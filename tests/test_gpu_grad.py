@@ -6,7 +6,11 @@ truncation, by the physical statevector; the GPU runs the same circuits
 with the oracle's records forced, checkpointed per stretch, and its adjoint
 pass (stn_backward) must give the same gradient: FP64 to 1e-8 and FP32 to
 1e-4 relative to the largest entry.  Shots whose truncation is
-ill-conditioned at a binding cut are skipped, as in the parity tests.
+ill-conditioned at a binding cut are skipped, as in the parity tests, and so
+are shots where the chi decision at some cut is within a factor MIN_MARGIN of
+the relative cut eps: whether such a step counts as truncated (and gets a
+frozen projector) is then set by rounding: the GPU's squared Schmidt values
+near the cut carry errors of about a tenth of eps times their sum.
 """
 import sys
 
@@ -21,8 +25,9 @@ from tests._circuits import entangling_circuit
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-8, "fp32": 1e-4}
-EPS = {"fp64": 1e-16, "fp32": 1e-14}
+EPS = {"fp64": 1e-14, "fp32": 1e-12}
 MAX_SENS = {"fp64": 1e6, "fp32": 30.0}
+MIN_MARGIN = 10.0
 
 
 @pytest.fixture(scope="module")
@@ -47,7 +52,7 @@ def oracle_case(circ, chi, prec):
         tapes.append(t)
         r = ostn.run_shot(circ, s, chi_max=chi, eps_cut=EPS[prec])
         recs.append(r.record)
-        sens.append(r.cut_sensitivity)
+        sens.append((r.cut_sensitivity, r.flag_margin))
     return tapes, np.array(recs, np.uint8), sens
 
 
@@ -60,7 +65,8 @@ def check(A, circ, chi, prec, segments=None):
     assert not run.adjoint_truncated.any(), "adjoint bond cap reached"
     used = 0
     for s, t in enumerate(tapes):
-        if sens[s] > MAX_SENS[prec]:
+        if sens[s][0] > MAX_SENS[prec] or sens[s][1] < MIN_MARGIN:
+            say(f"  shot {s}: skipped (cut sensitivity {sens[s][0]:.3g}, chi decision margin {sens[s][1]:.3g})")
             continue
         used += 1
         go = G.adjoint_gradient(t)
@@ -85,7 +91,7 @@ def test_gradient_matches_oracle(A, prec, chi):
 def test_gradient_d3_memory(A, chi):
     """d=3 memory experiment, 2 rounds, one angle per rotation instance (the
     c4 parametrisation at d=3), Pauli noise; chi 64 is exact, chi 4 binds."""
-    circ = W.memory_circuit(3, 2, 2, seed=5, theta_nn=0.1, p=0.02, per_layer_params=True)
+    circ = W.memory_circuit(3, 2, 4, seed=5, theta_nn=0.1, p=0.02, per_layer_params=True)
     check(A, circ, chi, "fp64")
 
 

@@ -18,7 +18,7 @@ from paper_2605_29514_amd import workload as W
 
 pytestmark = pytest.mark.gpu
 
-EPS = {"fp64": 1e-16, "fp32": 1e-14}
+EPS = {"fp64": 1e-14, "fp32": 1e-12}
 PTOL = {"fp64": 1e-10, "fp32": 1e-5}
 # Shots whose worst binding cut has s_k^2 / (s_k^2 - s_{k+1}^2) above this are
 # ill-conditioned at the working precision (the kept subspace turns by about
@@ -132,7 +132,7 @@ def test_clifford_only_matches_stabilizer_and_oracle(B, d):
     for s in range(0, 70, 7):
         rec, _ = chp.run_shot(circ, s)
         assert np.array_equal(g["records"][s], np.array(rec, np.uint8)), s
-    ores = {s: ostn.run_shot(circ, s, chi_max=4, eps_cut=1e-16) for s in (0, 13, 69)}
+    ores = {s: ostn.run_shot(circ, s, chi_max=4, eps_cut=EPS["fp64"]) for s in (0, 13, 69)}
     check_tableau(g["sim"], ores, ores.keys())
     assert np.all(g["sim"].bonds() == 1)
     assert np.all(np.isin(np.round(g["prob"], 15), [0.5, 1.0]))
@@ -188,14 +188,15 @@ def test_per_shot_theta(B, mode):
 def test_layer_modes_agree(B, prec, threads):
     """The fused per-shot layer kernel (any block size) and the per-step
     kernels give the same records and probabilities (up to rounding order)
-    on 96 shots."""
+    on 96 shots.  The two schedules round independently, so two FP32 results
+    each within the FP32 bound (1e-5) of the oracle agree to twice that."""
     circ = W.memory_circuit(3, 2, 96, seed=43, theta_law="per_coupling", nnn=True, p=0.01)
     a = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=1)
     b = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=2, layer_threads=threads)
     same = np.all(a["records"] == b["records"], axis=1)
     assert same.mean() > 0.95
     rel = np.abs(a["prob"][same] - b["prob"][same]) / a["prob"][same]
-    assert rel.max() <= (1e-10 if prec == "fp64" else 1e-5)
+    assert rel.max() <= (2e-10 if prec == "fp64" else 2e-5)
 
 
 def test_forced_zero_probability_is_reported(B):

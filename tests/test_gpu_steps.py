@@ -50,7 +50,7 @@ def random_frame(n, rng, k):
 def one_case(B, prec, seed, n=10, chi_state=8, chi_max=8, kind="rotate"):
     import torch
     rng = np.random.default_rng(seed)
-    eps = 1e-16 if prec == "fp64" else 1e-14
+    eps = 1e-14 if prec == "fp64" else 1e-12
     state = random_state(n, min(chi_state, chi_max), rng)
     gates = random_frame(n, rng, int(rng.integers(0, 25)))
     sim = B.Simulator(n, 1, chi_max, prec, eps)
