@@ -11,8 +11,8 @@
 // there are few shots or large bonds.
 //
 // Small operands live in one dynamic LDS region that the phases overlay
-// (QR matrix, GEMM staging, Jacobi matrices); operands beyond its size stay
-// in the shot's global scratch, so every bond up to chi_max is handled.
+// (QR matrix, GEMM staging, the eigen-solve matrix); operands beyond its size
+// stay in the shot's global scratch, so every bond up to chi_max is handled.
 #include "linalg.h"
 
 #include <algorithm>
@@ -21,30 +21,45 @@ namespace {
 
 using namespace stnk;
 
-constexpr int kLdsEigN = 32;              // Jacobi G and V in LDS up to this order
 constexpr int kLdsQrRows = 64;            // reflector vectors in LDS up to this many rows
 constexpr size_t kLdsQrMat = 16 * 1024;   // QR operand in LDS up to this many bytes
-constexpr int kLdsPairs = 64;             // Jacobi pair tables in LDS up to this order
+constexpr int kEigIdx = 64;               // eigen-solve index / pair tables in LDS up to this order
+constexpr int kJacLdsN = 32;              // FP64 path: Jacobi G and V in LDS up to this order
+constexpr int kEigLdsMax = 64;            // FP32 path: factor in LDS up to this order
 
-// Dynamic LDS layout (bytes).  U: union of the phase operands.
+// Dynamic LDS layout (bytes): small arrays at fixed offsets, then one
+// region that the phases overlay (GEMM staging, QR operand, the eigen-solve
+// matrices with padded rows).  The region holds the FP64 path's Jacobi G and
+// V up to order 32, or the FP32 path's factor up to order eig_n (a launch
+// parameter, eig_lds_order).
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kU = cmax(cmax(2 * kLdsEigN * (kLdsEigN + 1) * sizeof(c64), kLdsQrMat), GemmStage<double>::bytes);
-constexpr size_t kVs = kU;                                    // c64[kLdsQrRows]
-constexpr size_t kVd = kVs + kLdsQrRows * sizeof(c64);       // double[2 kLdsQrRows]
-constexpr size_t kPe = kVd + 2 * kLdsQrRows * sizeof(double);  // c64[kLdsPairs/2 + 1]
-constexpr size_t kPc = kPe + (kLdsPairs / 2 + 1) * sizeof(c64);
-constexpr size_t kPs = kPc + (kLdsPairs / 2 + 1) * sizeof(double);
-constexpr size_t kPos = kPs + (kLdsPairs / 2 + 1) * sizeof(double);
-constexpr size_t kPp = kPos + (kLdsPairs + 2) * sizeof(int);
-constexpr size_t kPq = kPp + (kLdsPairs / 2 + 1) * sizeof(int);
-constexpr size_t kWp = (kPq + (kLdsPairs / 2 + 1) * sizeof(int) + 15) / 16 * 16;
-constexpr size_t lds_bytes(int nt) { return kWp + nt * sizeof(c64); }
+constexpr int kPh = kEigIdx / 2 + 1;                            // pair-table length
+constexpr size_t kVs = 0;                                       // c64[kLdsQrRows]
+constexpr size_t kVd = kVs + kLdsQrRows * sizeof(c64);          // double[2 kLdsQrRows]
+constexpr size_t kDg = kVd + 2 * kLdsQrRows * sizeof(double);   // double[kEigIdx]
+constexpr size_t kPe = kDg + kEigIdx * sizeof(double);          // c64[kPh]
+constexpr size_t kPc = kPe + kPh * sizeof(c64);                 // double[kPh]
+constexpr size_t kPs = kPc + kPh * sizeof(double);              // double[kPh]
+constexpr size_t kPiv = kPs + kPh * sizeof(double);             // int[kEigIdx]
+constexpr size_t kPos = kPiv + kEigIdx * sizeof(int);           // int[kEigIdx + 2]
+constexpr size_t kPp = kPos + (kEigIdx + 2) * sizeof(int);      // int[kPh]
+constexpr size_t kPq = kPp + kPh * sizeof(int);                 // int[kPh]
+constexpr size_t kWp = (kPq + kPh * sizeof(int) + 15) / 16 * 16;  // c64[NT]
+constexpr size_t kUfix = cmax(kLdsQrMat, GemmStage<double>::bytes);
+constexpr size_t u_off(int nt) { return (kWp + nt * sizeof(c64) + 255) / 256 * 256; }
+constexpr size_t eig_region(bool fp64, int en) {
+  return fp64 ? 2 * (size_t)kJacLdsN * (kJacLdsN + 1) * sizeof(c64) : (size_t)en * (en + 1) * sizeof(c64);
+}
+constexpr size_t lds_bytes(int nt, bool fp64, int en) { return u_off(nt) + cmax(kUfix, eig_region(fp64, en)); }
+// FP32 path: factors up to order 64 in LDS when chi_max is 17..32 (every
+// doubled bond then fits, at ~70 KB per block); otherwise up to 32 (~22 KB)
+// and larger orders in the shot's global scratch.
+inline int eig_lds_order(int chi) { return (2 * chi > 32 && 2 * chi <= kEigLdsMax) ? kEigLdsMax : 32; }
 
-// Global fallbacks in the shot's J scratch (bytes): reflector vectors for
-// up to 4 chi rows, then the pair tables for orders up to 2 chi.
+// Global fallbacks in the shot's J scratch: reflector vectors for up to
+// 4 chi + 2 rows, eigen-solve index and pair tables for orders up to 2 chi + 2.
 struct Fallback {
-  c64 *vs; double *vd;
-  c64 *pe; double *pc, *ps; int *pos, *pp, *pq;
+  c64 *vs, *pe; double *vd, *dg, *pc, *ps; int *piv, *pos, *pp, *pq;
 };
 __device__ inline Fallback fallback(const MpsDev &m, int s) {
   char *b = reinterpret_cast<char *>(m.J) + (size_t)s * m.J_cap;
@@ -53,9 +68,11 @@ __device__ inline Fallback fallback(const MpsDev &m, int s) {
   f.vs = reinterpret_cast<c64 *>(b);
   f.pe = f.vs + rows;
   f.vd = reinterpret_cast<double *>(f.pe + P / 2 + 1);
-  f.pc = f.vd + 2 * rows;
+  f.dg = f.vd + 2 * rows;
+  f.pc = f.dg + P;
   f.ps = f.pc + P / 2 + 1;
-  f.pos = reinterpret_cast<int *>(f.ps + P / 2 + 1);
+  f.piv = reinterpret_cast<int *>(f.ps + P / 2 + 1);
+  f.pos = f.piv + P;
   f.pp = f.pos + P + 2;
   f.pq = f.pp + P / 2 + 1;
   return f;
@@ -64,7 +81,7 @@ __device__ inline Fallback fallback(const MpsDev &m, int s) {
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void blk_gemm(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
                          const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, char *lds) {
-  gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds);
+  gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds + u_off(NT));
   __syncthreads();
 }
 
@@ -84,7 +101,7 @@ __device__ void blk_qr(const MpsDev &m, int s, int rows, int cols, cplx<T> *A, c
   double *vd = rows <= kLdsQrRows ? reinterpret_cast<double *>(lds + kVd) : f.vd;
   c64 *wp = reinterpret_cast<c64 *>(lds + kWp);
   if ((size_t)rows * cols * sizeof(cplx<T>) <= kLdsQrMat) {
-    cplx<T> *Al = reinterpret_cast<cplx<T> *>(lds);
+    cplx<T> *Al = reinterpret_cast<cplx<T> *>(lds + u_off(NT));
     blk_copy<T, NT>(Al, A, rows * cols);
     qr_block<T, NT>(rows, cols, Al, Qd, qt, Rd, vs, vd, wp);
   } else {
@@ -177,7 +194,7 @@ struct SiteOps {
 // and renormalises.
 template <typename T, int NT>
 __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &so, c64 ca, c64 cb, bool unitary,
-                          int &c, char *lds, PhaseClock &clk, int *sweeps, int cls) {
+                          int &c, char *lds, int eig_n, PhaseClock &clk, int *sweeps, int cls) {
   const bool f64c = m.prof && cls == K_LAYER;   // FP64 share is tracked for the layer class
   const int tid = threadIdx.x;
   int *b = bnd(m, s), *w = wbd(m, s);
@@ -322,32 +339,63 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
       blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
     }
     clk.lap(m, 5);
+    const c64 *Vsel;                          // sorted eigenvectors, nn x nn
     {
       const Fallback f = fallback(m, s);
-      const bool lp = nn <= kLdsPairs;
-      int *pos = lp ? reinterpret_cast<int *>(lds + kPos) : f.pos;
-      int *pp = lp ? reinterpret_cast<int *>(lds + kPp) : f.pp;
-      int *pq = lp ? reinterpret_cast<int *>(lds + kPq) : f.pq;
-      double *pc = lp ? reinterpret_cast<double *>(lds + kPc) : f.pc;
-      double *ps = lp ? reinterpret_cast<double *>(lds + kPs) : f.ps;
-      c64 *pe = lp ? reinterpret_cast<c64 *>(lds + kPe) : f.pe;
-      c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
-      int ldw = nn;
-      if (nn <= kLdsEigN) {                   // rotate in LDS (rows padded), write the sorted vectors back
-        c64 *Gl = reinterpret_cast<c64 *>(lds);
-        ldw = nn + 1;
-        for (int e = tid; e < nn * nn; e += NT) {
-          const int r0 = e / nn, c0 = e - r0 * nn;
-          Gl[r0 * ldw + c0] = Gg[e];
+      const bool li = nn <= kEigIdx;
+      int *pos = li ? reinterpret_cast<int *>(lds + kPos) : f.pos;
+      double fe;
+      if constexpr (sizeof(T) == 8) {
+        // FP64 path: two-sided Jacobi on rho (relative accuracy down to the
+        // smallest kept values); G and V in LDS up to order 32
+        int *pp = li ? reinterpret_cast<int *>(lds + kPp) : f.pp;
+        int *pq = li ? reinterpret_cast<int *>(lds + kPq) : f.pq;
+        double *pc = li ? reinterpret_cast<double *>(lds + kPc) : f.pc;
+        double *ps = li ? reinterpret_cast<double *>(lds + kPs) : f.ps;
+        c64 *pe = li ? reinterpret_cast<c64 *>(lds + kPe) : f.pe;
+        c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
+        int ldw = nn;
+        if (nn <= kJacLdsN) {
+          c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
+          ldw = nn + 1;
+          int r0 = tid / nn, c0 = tid - (tid / nn) * nn;
+          const int dr0 = NT / nn, dc0 = NT - (NT / nn) * nn;
+          for (int e = tid; e < nn * nn; e += NT, r0 += dr0, c0 += dc0) {
+            if (c0 >= nn) { c0 -= nn; ++r0; }
+            Gl[r0 * ldw + c0] = Gg[e];
+          }
+          __syncthreads();
+          Gw = Gl;
+          Vw = Gl + kJacLdsN * (kJacLdsN + 1);
         }
-        __syncthreads();
-        Gw = Gl;
-        Vw = Gl + kLdsEigN * (kLdsEigN + 1);
+        jacobi_block<NT>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, sweeps,
+                         jac_abs<T>(), jac_rel<T>());
+        fe = 36.0 * nn * nn * (double)nn;
+        Vsel = Gg;
+      } else {
+        // FP32 path: pivoted Cholesky + one-sided Jacobi on the factor
+        int *piv = li ? reinterpret_cast<int *>(lds + kPiv) : f.piv;
+        double *dg = li ? reinterpret_cast<double *>(lds + kDg) : f.dg;
+        c64 *Gw = Gg;
+        int ldw = nn;
+        if (nn <= eig_n) {                    // factor in LDS (rows padded by one)
+          c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
+          ldw = nn + 1;
+          int r0 = tid / nn, c0 = tid - (tid / nn) * nn;
+          const int dr0 = NT / nn, dc0 = NT - (NT / nn) * nn;
+          for (int e = tid; e < nn * nn; e += NT, r0 += dr0, c0 += dc0) {
+            if (c0 >= nn) { c0 -= nn; ++r0; }
+            Gl[r0 * ldw + c0] = Gg[e];
+          }
+          __syncthreads();
+          Gw = Gl;
+        }
+        fe = eig_psd<NT>(nn, Gw, ldw, m.ev + s * m.ev_cap, m.V + s * m.V_cap, m.err, piv, pos, dg, sweeps,
+                         chol_tol(m.eps_cut, nn), eig_conv_tol<T>(), eig_rot_tol<T>());
+        Vsel = m.V + s * m.V_cap;
       }
-      jacobi_block<NT>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, sweeps,
-                       jac_abs<T>(), jac_rel<T>());
       if (tid == 0) {
-        const double f64 = gemm_flops(nn, nn, Lx) + 36.0 * nn * nn * (double)nn;
+        const double f64 = gemm_flops(nn, nn, Lx) + fe;
         add_work(m, cls, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
         if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
         if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)*sweeps);
@@ -355,7 +403,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
       clk.lap(m, 6);
     }
     cplx<T> *Vt = scr<T>(m.Vt, m.Vt_cap, s);
-    const int k = select_body<T, NT>(m, s, j, Vt);
+    const int k = select_body<T, NT>(m, s, j, Vsel, Vt);
     cplx<T> *Nn = scr<T>(m.N, m.N_cap, s);
     blk_gemm<T, T, T, T, NT>(Lx, k, nn, X, nn, 0, Vt, k, 0, Nn, k, lds);
     const int M = 2 * w[j - 1];
@@ -375,7 +423,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, const uint64_t *psgn,
                                               int W, int SW, const double *theta, int64_t stride,
-                                              RotLayer L) {
+                                              RotLayer L, int eig_n) {
   extern __shared__ __align__(16) char lds[];
   const int s = blockIdx.x, tid = threadIdx.x;
   __shared__ c64 cf[2];
@@ -394,7 +442,7 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
     }
     __syncthreads();
     const SiteOps so{nullptr, bx, bz, l};
-    shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], true, c, lds, clk, &sweeps, K_LAYER);
+    shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], true, c, lds, eig_n, clk, &sweeps, K_LAYER);
   }
 }
 
@@ -407,7 +455,7 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_meas(MpsDev m, const uint64_t *snap_sign, const c64 *ops, const c64 *eops,
                                              MeasStep a, const double *u, const uint8_t *forced, uint8_t *out,
-                                             double *prob, uint64_t *negmask, uint64_t *mmask) {
+                                             double *prob, uint64_t *negmask, uint64_t *mmask, int eig_n) {
   extern __shared__ __align__(16) char lds[];
   const int s = blockIdx.x, tid = threadIdx.x;
   __shared__ c64 cf[2];
@@ -478,7 +526,7 @@ __global__ void __launch_bounds__(NT) k_meas(MpsDev m, const uint64_t *snap_sign
   }
   __syncthreads();
   const SiteOps so{ops, nullptr, nullptr, l};
-  shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], false, c, lds, clk, &sweeps, K_EXPECT);
+  shot_step<T, NT>(m, s, l, r, so, cf[0], cf[1], false, c, lds, eig_n, clk, &sweeps, K_EXPECT);
 }
 
 __global__ void k_clear_words(uint64_t *a, uint64_t *b, int n) {
@@ -488,24 +536,26 @@ __global__ void k_clear_words(uint64_t *a, uint64_t *b, int n) {
 template <typename T, int NT>
 void launch_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
                   const double *d_theta, int64_t stride, const RotLayer &L, hipStream_t st) {
-  KLAUNCH(K_LAYER, (k_layer<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT), st, m, d_pbits, d_psgn, W, SW,
-          d_theta, stride, L);
+  const int en = eig_lds_order(m.chi);
+  KLAUNCH(K_LAYER, (k_layer<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_pbits, d_psgn, W, SW,
+          d_theta, stride, L, en);
 }
 
 }  // namespace
 
 size_t layer_fallback_bytes(int chi) {
-  const size_t rows = 4 * (size_t)chi + 2, P = 2 * (size_t)chi + 2;
-  return rows * sizeof(c64) + (P / 2 + 1) * sizeof(c64) + 2 * rows * sizeof(double) +
-         2 * (P / 2 + 1) * sizeof(double) + (P + 2) * sizeof(int) + 2 * (P / 2 + 1) * sizeof(int) + 64;
+  const size_t rows = 4 * (size_t)chi + 2, P = 2 * (size_t)chi + 2, H = P / 2 + 1;
+  return rows * sizeof(c64) + H * sizeof(c64) + 2 * rows * sizeof(double) + P * sizeof(double) +
+         2 * H * sizeof(double) + P * sizeof(int) + (P + 2) * sizeof(int) + 2 * H * sizeof(int) + 64;
 }
 
 template <typename T, int NT>
 void launch_meas(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *d_ops, const c64 *d_eops,
                  const MeasStep &a, const double *d_u, const uint8_t *d_forced, uint8_t *d_out, double *d_prob,
                  uint64_t *d_negmask, uint64_t *d_mmask, hipStream_t st) {
-  KLAUNCH(K_EXPECT, (k_meas<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT), st, m, d_snap_sign, d_ops, d_eops, a, d_u,
-          d_forced, d_out, d_prob, d_negmask, d_mmask);
+  const int en = eig_lds_order(m.chi);
+  KLAUNCH(K_EXPECT, (k_meas<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_snap_sign, d_ops, d_eops, a, d_u,
+          d_forced, d_out, d_prob, d_negmask, d_mmask, en);
 }
 
 template <typename T>
@@ -534,7 +584,8 @@ hipError_t layer_prepare() {
                        (const void *)k_meas<T, 64>, (const void *)k_meas<T, 128>, (const void *)k_meas<T, 256>};
   const int nts[6] = {64, 128, 256, 64, 128, 256};
   for (int i = 0; i < 6; ++i) {
-    hipError_t e2 = hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(nts[i]));
+    hipError_t e2 = hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds_bytes(nts[i], sizeof(T) == 8, kEigLdsMax));
     if (e == hipSuccess) e = e2;
   }
   return e;

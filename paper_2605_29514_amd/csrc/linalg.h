@@ -465,21 +465,243 @@ __device__ void jacobi_block(int nn, c64 *G, int ld, c64 *V, double *ev, c64 *Vo
   __syncthreads();
 }
 
-// Stopping rule of the Jacobi solve per storage precision.  FP64 states
-// converge the off-diagonal to 1e-15 relative (floor 1e-18 of the trace).
-// FP32 states store the kept vectors in FP32 (relative rounding 6e-8), so
-// 1e-10 relative with a 1e-15 floor (the rounding level of a Gram of FP32
-// data) already leaves the eigenvectors far more accurate than stored.
-template <typename T> __device__ inline double jac_abs() { return sizeof(T) == 8 ? 1e-18 : 1e-15; }
-template <typename T> __device__ inline double jac_rel() { return sizeof(T) == 8 ? 1e-15 : 1e-10; }
+// Stopping rule of the two-sided Jacobi, which serves the FP64 path: the
+// off-diagonal converges to 1e-15 relative (floor 1e-18 of the trace).  Its
+// rotations keep the relative accuracy of the small kept eigenvalues, which
+// the 1e-10 bound of FP64 probabilities needs.
+template <typename T> __device__ inline double jac_abs() { return 1e-18; }
+template <typename T> __device__ inline double jac_rel() { return 1e-15; }
+
+// ------------------------------------------------ eigen-solve (FP64)
+// Block-wide argmax of (v, i): largest v, ties to the smaller i; every
+// thread receives the result.  Barriers before and after the exchange, so
+// calls may follow each other directly.
+template <int NT>
+__device__ void bargmax(double v, int i, double &vo, int &io) {
+  __shared__ double rv[NT / 64 > 0 ? NT / 64 : 1];
+  __shared__ int ri[NT / 64 > 0 ? NT / 64 : 1];
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v2 = __shfl_xor(v, o, 64);
+    const int i2 = __shfl_xor(i, o, 64);
+    if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { rv[threadIdx.x >> 6] = v; ri[threadIdx.x >> 6] = i; }
+  __syncthreads();
+  vo = rv[0];
+  io = ri[0];
+  for (int w = 1; w < NT / 64; ++w)
+    if (rv[w] > vo || (rv[w] == vo && ri[w] < io)) { vo = rv[w]; io = ri[w]; }
+}
+
+// Eigen-decomposition of a Hermitian positive semi-definite matrix G
+// (nn x nn, leading dimension ld, in LDS or global memory; overwritten):
+// the reduced density of a truncation step, whose numerical rank is often
+// well below its order.
+//
+//  1. Pivoted Cholesky, right-looking and in place: at step k the largest
+//     remaining diagonal d of the Schur complement picks the pivot p, row p
+//     becomes R_k = S_p / sqrt(d) (zero at the columns pivoted before) and
+//     the Schur complement of the other indices loses R_k^H R_k.  It stops
+//     once d <= chol_tol tr G; the part not captured has eigenvalues at most
+//     (nn - r) chol_tol tr G.  Then G = R^H R with the r rows of R in rows
+//     piv[0..r) of G.
+//  2. One-sided Jacobi on those rows: each round rotates r/2 disjoint row
+//     pairs (circle order), a pair (x, y) with a = |x|^2, b = |y|^2,
+//     c = x y^H being replaced by (cs x - sg y, conj(sg) x + cs y),
+//     sg = sn c / |c|, where t = sn / cs is the root of smaller modulus of
+//     t^2 + 2 t (b - a) / 2|c| - 1 = 0, which makes the pair orthogonal.
+//     Pairs with |c| > rot_tol sqrt(a b) are rotated; sweeps repeat until
+//     no pair had |c| > conv_tol sqrt(a b).  With rot_tol below conv_tol
+//     the last sweep leaves the rows orthogonal to rounding level: the
+//     eigenvectors come out orthonormal as well as the rotations that an
+//     accumulated two-sided solve would give.  Pivoting orders the rows by
+//     decreasing weight, which speeds the sweeps up.
+//  3. The rows are now orthogonal, so G = sum_c u_c u_c^H with u_c = row
+//     c^H: eigenvalue |u_c|^2, eigenvector u_c / |u_c|.  ev <- eigenvalues
+//     in descending order (0 past r); column j of Vout (nn x nn, leading
+//     dimension nn, distinct from G) <- the eigenvector of ev[j] for j < r
+//     (e_0 when r = 0).
+// Scratch: piv, pos (nn ints), dg (nn doubles).  Returns (to every thread)
+// the flops executed; *sweeps_out (thread 0) <- Jacobi sweeps.
+constexpr int kEigTpp = 8;        // threads per row pair
+constexpr int kEigMaxSweeps = 40;
+
+template <int NT>
+__device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *err, int *piv, int *pos,
+                          double *dg, int *sweeps_out, double chol_tol, double conv_tol, double rot_tol) {
+  const int tid = threadIdx.x;
+  double trp = 0;
+  for (int i = tid; i < nn; i += NT) {
+    const double d = G[(size_t)i * ld + i].x;
+    dg[i] = d;
+    trp += d;
+  }
+  const double tr = bsum<NT>(trp);
+  if (tid == 0 && (!(tr == tr) || isinf(tr))) atomicOr(err, STN_ERR_NUMERIC);
+  const double thr = chol_tol * tr;
+  double flops = 0;
+  // 1. pivoted Cholesky
+  int r = 0;
+  {
+    double v = -INFINITY;
+    int vi = 0x7fffffff;
+    for (int i = tid; i < nn; i += NT)
+      if (dg[i] > v) { v = dg[i]; vi = i; }
+    double d;
+    int p;
+    bargmax<NT>(v, vi, d, p);
+    const int di = NT / nn, dj = NT - (NT / nn) * nn;
+    for (int k = 0; k < nn; ++k) {
+      if (!(d > thr) || !(tr > 0)) break;
+      const double sd = sqrt(d), is = 1.0 / sd;
+      for (int j = tid; j < nn; j += NT) {
+        c64 x;
+        if (j == p) x = mk<double>(sd, 0);
+        else if (dg[j] == -INFINITY) x = mk<double>(0, 0);
+        else x = is * G[(size_t)p * ld + j];
+        G[(size_t)p * ld + j] = x;
+      }
+      if (tid == 0) piv[k] = p;
+      __syncthreads();
+      const c64 *R = G + (size_t)p * ld;
+      int i = tid / nn, j = tid - (tid / nn) * nn;
+      for (int e = tid; e < nn * nn; e += NT, i += di, j += dj) {
+        if (j >= nn) { j -= nn; ++i; }
+        if (i == p || j == p || i == j || dg[i] == -INFINITY || dg[j] == -INFINITY) continue;
+        G[(size_t)i * ld + j] = G[(size_t)i * ld + j] - cj(R[i]) * R[j];
+      }
+      v = -INFINITY;
+      vi = 0x7fffffff;
+      for (int q = tid; q < nn; q += NT) {
+        if (q == p) { dg[q] = -INFINITY; continue; }
+        const double dq = dg[q];
+        if (dq == -INFINITY) continue;
+        const double nd = dq - norm2(R[q]);
+        dg[q] = nd;
+        if (nd > v) { v = nd; vi = q; }
+      }
+      flops += 8.0 * (double)(nn - k - 1) * (nn - k - 1);
+      r = k + 1;
+      bargmax<NT>(v, vi, d, p);
+    }
+  }
+  // 2. one-sided Jacobi on the rows piv[0..r)
+  int sweeps = 0;
+  if (r >= 2) {
+    constexpr int TPP = kEigTpp, GP = NT / kEigTpp;
+    const int P = r + (r & 1), H = P / 2;
+    const int li = tid % TPP, gi = tid / TPP;
+    for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
+      int rot = 0;
+      for (int rnd = 0; rnd < P - 1; ++rnd) {
+        for (int pi = gi; pi < H; pi += GP) {
+          // positions 1..P-1 shift by one per round (circle method), 0 stays
+          int x = pi - 1 - rnd, y = P - 2 - pi - rnd;
+          if (x < 0) x += P - 1;
+          if (y < 0) y += P - 1;
+          int p = pi == 0 ? 0 : 1 + x, q = 1 + y;
+          if (p > q) { const int t = p; p = q; q = t; }
+          if (q >= r) continue;
+          c64 *X = G + (size_t)piv[p] * ld, *Y = G + (size_t)piv[q] * ld;
+          double a = 0, b = 0;
+          c64 cc = mk<double>(0, 0);
+          for (int j = li; j < nn; j += TPP) {
+            const c64 xv = X[j], yv = Y[j];
+            a += norm2(xv);
+            b += norm2(yv);
+            cc = cc + xv * cj(yv);
+          }
+#pragma unroll
+          for (int o = 1; o < TPP; o <<= 1) {
+            a += __shfl_xor(a, o, TPP);
+            b += __shfl_xor(b, o, TPP);
+            cc.x += __shfl_xor(cc.x, o, TPP);
+            cc.y += __shfl_xor(cc.y, o, TPP);
+          }
+          const double h = sqrt(norm2(cc)), ab = sqrt(a * b);
+          if (h > 0 && h > rot_tol * ab) {
+            const double d = b - a;
+            const double t = (d >= 0 ? 2.0 : -2.0) * h / (fabs(d) + sqrt(d * d + 4.0 * h * h));
+            const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs, ih = sn / h;
+            const c64 sg = mk<double>(cc.x * ih, cc.y * ih), sgc = cj(sg);
+            for (int j = li; j < nn; j += TPP) {
+              const c64 xv = X[j], yv = Y[j];
+              X[j] = cs * xv - sg * yv;
+              Y[j] = sgc * xv + cs * yv;
+            }
+            if (h > conv_tol * ab) rot = 1;
+          }
+        }
+        __syncthreads();
+      }
+      sweeps = sweep + 1;
+      if (bsum<NT>(rot) == 0) break;
+      if (sweeps == kEigMaxSweeps && tid == 0) atomicOr(err, STN_ERR_EIGEN);
+    }
+    flops += (double)sweeps * (r * (r - 1) / 2) * 40.0 * nn;
+  }
+  // 3. eigenvalues (squared row norms), their order, eigenvectors
+  {
+    constexpr int TPP = kEigTpp, GP = NT / kEigTpp;
+    const int li = tid % TPP, gi = tid / TPP;
+    for (int i0 = 0; i0 < r; i0 += GP) {
+      const int i = i0 + gi;
+      double a = 0;
+      if (i < r) {
+        const c64 *X = G + (size_t)piv[i] * ld;
+        for (int j = li; j < nn; j += TPP) a += norm2(X[j]);
+      }
+#pragma unroll
+      for (int o = 1; o < TPP; o <<= 1) a += __shfl_xor(a, o, TPP);
+      if (i < r && li == 0) dg[i] = a;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += NT) {
+    const double l = dg[i];
+    int rank = 0;
+    for (int j = 0; j < r; ++j) {
+      const double lj = dg[j];
+      rank += (lj > l) || (lj == l && j < i);
+    }
+    ev[rank] = l;
+    pos[i] = rank;
+  }
+  for (int i = r + tid; i < nn; i += NT) ev[i] = 0;
+  __syncthreads();
+  for (int e = tid; e < r * nn; e += NT) {
+    const int c = e / nn, i = e - c * nn;
+    const double nr = dg[c];
+    const double inv = nr > 0 ? 1.0 / sqrt(nr) : 0.0;
+    Vout[(size_t)i * nn + pos[c]] = inv * cj(G[(size_t)piv[c] * ld + i]);
+  }
+  if (r == 0)
+    for (int i = tid; i < nn; i += NT) Vout[(size_t)i * nn] = mk<double>(i == 0 ? 1.0 : 0.0, 0);
+  if (sweeps_out && tid == 0) *sweeps_out = sweeps;
+  __syncthreads();
+  return flops;
+}
+
+// Tolerances of the one-sided Jacobi, which serves the FP32 path.  Its
+// states keep the vectors in FP32 (relative rounding 6e-8), so rows
+// orthogonal to 1e-10 are already more accurate than stored.  (Forming rho
+// squares the condition of the small kept directions: their eigenvectors
+// carry errors ~ eps_64 tr / lambda, up to ~3e-11 of the state per step,
+// far below FP32 rounding but above what the FP64 bound allows.)
+template <typename T> __device__ inline double eig_conv_tol() { return 1e-10; }
+template <typename T> __device__ inline double eig_rot_tol() { return 1e-10; }
+// Pivoted-Cholesky cut: captures every eigenvalue above eps_cut tr G (the
+// truncation threshold), but not below a few roundings of tr G.
+__device__ inline double chol_tol(double eps_cut, int nn) { return fmax(eps_cut / (nn > 0 ? nn : 1), 4e-16); }
 
 // ------------------------------------------------------------ truncation
 // Keep k' = min(chi_max, #{lambda_i > eps sum lambda}, 2^min(j, n-j)) largest
 // (at least 1); the discarded weight updates the fidelity; Vt = V[:, :k']
 // (nn x k'); site j <- Vt^H as (k', 2, wb[j+1]); bond[j] = k',
-// bond[j+1] = wb[j+1].  V (sorted eigenvectors) and ev are read from G, ev.
+// bond[j+1] = wb[j+1].  The sorted eigenvectors (ld nn) are read from V.
 template <typename T, int NT>
-__device__ int select_body(const MpsDev &m, int s, int j, cplx<T> *Vt) {
+__device__ int select_body(const MpsDev &m, int s, int j, const c64 *V, cplx<T> *Vt) {
   int *w = wbd(m, s);
   const int nn = 2 * w[j + 1];
   const double *ev = m.ev + s * m.ev_cap;
@@ -510,7 +732,6 @@ __device__ int select_body(const MpsDev &m, int s, int j, cplx<T> *Vt) {
   }
   __syncthreads();
   const int k = kk;
-  const c64 *V = m.G + s * m.G_cap;
   cplx<T> *site = slot<T>(m, j, s);
   for (int e = threadIdx.x; e < nn * k; e += NT) {
     int i = e / k, c = e % k;

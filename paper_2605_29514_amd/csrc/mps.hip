@@ -27,7 +27,9 @@ namespace {
 using namespace stnk;
 
 constexpr int TB = 256;          // threads per block of the per-step kernels
-constexpr int kEigLdsN = 32;     // Jacobi in LDS up to this order (2 x 16 KB)
+constexpr int kEigLdsN = 64;     // FP32 path: factor in LDS up to this order (66.5 KB)
+constexpr int kJacLdsN = 32;     // FP64 path: Jacobi G and V in LDS up to this order (2 x 16.5 KB)
+constexpr int kEigIdx = 1040;    // eigen-solve index / pair tables (orders up to 2 x 512 + 16)
 constexpr size_t kQrLdsMat = 16 * 1024;
 
 __device__ inline bool first_block() { return blockIdx.x == 0 && threadIdx.x == 0; }
@@ -185,42 +187,63 @@ __global__ void k_gram(MpsDev m, int j) {
     add_work(m, K_GRAM, gemm_flops(nn, nn, L), (double)sizeof(cplx<T>) * L * nn + 16.0 * nn * nn);
 }
 
+// FP64 states: two-sided Jacobi on rho (G and V in LDS up to order
+// kJacLdsN, sorted eigenvectors written back into G).  FP32 states: pivoted
+// Cholesky + one-sided Jacobi on the factor (in LDS up to order kEigLdsN,
+// eigenvectors into V).
 template <typename T>
 __global__ void k_eig(MpsDev m, int j) {
-  extern __shared__ char lds[];
+  extern __shared__ __align__(16) char lds[];
   const int s = blockIdx.x;
   const int nn = 2 * wbd(m, s)[j + 1];
-  c64 *Gl = reinterpret_cast<c64 *>(lds);                 // used when nn <= kEigLdsN
-  c64 *Vl = Gl + kEigLdsN * (kEigLdsN + 1);
-  int *pos = reinterpret_cast<int *>(Vl + kEigLdsN * (kEigLdsN + 1));
-  int *pp = pos + 1040, *pq = pp + 520;
-  double *pc = reinterpret_cast<double *>(pq + 520);
-  double *ps = pc + 520;
-  c64 *pe = reinterpret_cast<c64 *>(ps + 520);
   c64 *Gg = m.G + s * m.G_cap;
-  c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
-  int ldw = nn;
-  if (nn <= kEigLdsN) {       // small matrices: rotate in LDS (rows padded), write the sorted vectors back
-    ldw = nn + 1;
-    for (int e = threadIdx.x; e < nn * nn; e += TB) Gl[(e / nn) * ldw + e % nn] = Gg[e];
-    __syncthreads();
-    Gw = Gl;
-    Vw = Vl;
-  }
-  // eigenvectors are accumulated in V and written sorted into G (global)
   __shared__ int sweeps;
-  jacobi_block<TB>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg,
-               m.err, pos, pc, ps, pe, pp, pq, &sweeps,
-               jac_abs<T>(), jac_rel<T>());
-  // algorithmic work: a Hermitian eigendecomposition with vectors, ~9 n^3 real
-  // flops (x4 complex); bytes: read G, write eigenvalues and vectors.
-  if (threadIdx.x == 0) add_work(m, K_EIGEN, 36.0 * nn * nn * (double)nn, 16.0 * 2 * nn * nn + 8.0 * nn);
+  double fe;
+  if constexpr (sizeof(T) == 8) {
+    c64 *Gl = reinterpret_cast<c64 *>(lds);                 // used when nn <= kJacLdsN
+    c64 *Vl = Gl + kJacLdsN * (kJacLdsN + 1);
+    int *pos = reinterpret_cast<int *>(Vl + kJacLdsN * (kJacLdsN + 1));
+    int *pp = pos + kEigIdx, *pq = pp + kEigIdx / 2;
+    double *pc = reinterpret_cast<double *>(pq + kEigIdx / 2);
+    double *ps = pc + kEigIdx / 2;
+    c64 *pe = reinterpret_cast<c64 *>(ps + kEigIdx / 2);
+    c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
+    int ldw = nn;
+    if (nn <= kJacLdsN) {
+      ldw = nn + 1;
+      for (int e = threadIdx.x; e < nn * nn; e += TB) Gl[(e / nn) * ldw + e % nn] = Gg[e];
+      __syncthreads();
+      Gw = Gl;
+      Vw = Vl;
+    }
+    jacobi_block<TB>(nn, Gw, ldw, Vw, m.ev + s * m.ev_cap, Gg, m.err, pos, pc, ps, pe, pp, pq, &sweeps,
+                     jac_abs<T>(), jac_rel<T>());
+    fe = 36.0 * nn * nn * (double)nn;
+  } else {
+    double *dg = reinterpret_cast<double *>(lds);           // index arrays up to order kEigIdx
+    int *piv = reinterpret_cast<int *>(dg + kEigIdx), *pos = piv + kEigIdx;
+    c64 *Gl = reinterpret_cast<c64 *>(pos + kEigIdx);       // the factor when nn <= kEigLdsN
+    c64 *Gw = Gg;
+    int ldw = nn;
+    if (nn <= kEigLdsN) {
+      ldw = nn + 1;
+      for (int e = threadIdx.x; e < nn * nn; e += TB) Gl[(e / nn) * ldw + e % nn] = Gg[e];
+      __syncthreads();
+      Gw = Gl;
+    }
+    fe = eig_psd<TB>(nn, Gw, ldw, m.ev + s * m.ev_cap, m.V + s * m.V_cap, m.err, piv, pos, dg, &sweeps,
+                     chol_tol(m.eps_cut, nn), eig_conv_tol<T>(), eig_rot_tol<T>());
+  }
+  // work: the method's operation count; bytes: read G, write eigenvalues and vectors
+  if (threadIdx.x == 0) add_work(m, K_EIGEN, fe, 16.0 * 2 * nn * nn + 8.0 * nn);
   if (threadIdx.x == 0 && m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)sweeps);
 }
 
 template <typename T>
 __global__ void k_select(MpsDev m, int j) {
-  select_body<T, TB>(m, blockIdx.x, j, scr<T>(m.Vt, m.Vt_cap, blockIdx.x));
+  const int s = blockIdx.x;
+  const c64 *V = sizeof(T) == 8 ? m.G + s * m.G_cap : m.V + s * m.V_cap;
+  select_body<T, TB>(m, s, j, V, scr<T>(m.Vt, m.Vt_cap, s));
 }
 
 // N = X (L x nn) * Vt (nn x k')
@@ -547,8 +570,10 @@ template <typename T> void mps_sweep_lr(const MpsDev &m, int l, int r, hipStream
 }
 
 static size_t eig_lds() {
-  return 2 * kEigLdsN * (kEigLdsN + 1) * sizeof(c64) + 1040 * sizeof(int) + 2 * 520 * sizeof(int) +
-         2 * 520 * sizeof(double) + 520 * sizeof(c64);
+  const size_t f64 = 2 * (size_t)kJacLdsN * (kJacLdsN + 1) * sizeof(c64) + (size_t)kEigIdx * 2 * sizeof(int) +
+                     (size_t)kEigIdx / 2 * (2 * sizeof(double) + sizeof(c64));
+  const size_t f32 = (size_t)kEigIdx * (sizeof(double) + 2 * sizeof(int)) + (size_t)kEigLdsN * (kEigLdsN + 1) * sizeof(c64);
+  return f64 > f32 ? f64 : f32;
 }
 
 template <typename T> void mps_sweep_rl(const MpsDev &m, int l, int r, hipStream_t st) {
