@@ -474,23 +474,25 @@ template <typename T> __device__ inline double jac_rel() { return 1e-15; }
 
 // ------------------------------------------------ eigen-solve (FP64)
 // Block-wide argmax of (v, i): largest v, ties to the smaller i; every
-// thread receives the result.  Barriers before and after the exchange, so
-// calls may follow each other directly.
+// thread receives the result.  The partials go to buffer `buf` (0 or 1) of
+// the caller's rv / ri (2 x NT/64 entries each): calls that alternate the
+// buffer need only the one barrier inside, as long as some barrier
+// separates every call from the one two calls earlier.
 template <int NT>
-__device__ void bargmax(double v, int i, double &vo, int &io) {
-  __shared__ double rv[NT / 64 > 0 ? NT / 64 : 1];
-  __shared__ int ri[NT / 64 > 0 ? NT / 64 : 1];
+__device__ void bargmax(double v, int i, double &vo, int &io, double *rv, int *ri, int buf) {
+  constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
   for (int o = 32; o > 0; o >>= 1) {
     const double v2 = __shfl_xor(v, o, 64);
     const int i2 = __shfl_xor(i, o, 64);
     if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
   }
-  __syncthreads();
+  rv += buf * NW;
+  ri += buf * NW;
   if ((threadIdx.x & 63) == 0) { rv[threadIdx.x >> 6] = v; ri[threadIdx.x >> 6] = i; }
   __syncthreads();
   vo = rv[0];
   io = ri[0];
-  for (int w = 1; w < NT / 64; ++w)
+  for (int w = 1; w < NW; ++w)
     if (rv[w] > vo || (rv[w] == vo && ri[w] < io)) { vo = rv[w]; io = ri[w]; }
 }
 
@@ -531,6 +533,9 @@ template <int NT>
 __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *err, int *piv, int *pos,
                           double *dg, int *sweeps_out, double chol_tol, double conv_tol, double rot_tol) {
   const int tid = threadIdx.x;
+  constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
+  __shared__ double amv[2 * NW];
+  __shared__ int ami[2 * NW];
   double trp = 0;
   for (int i = tid; i < nn; i += NT) {
     const double d = G[(size_t)i * ld + i].x;
@@ -550,7 +555,7 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
       if (dg[i] > v) { v = dg[i]; vi = i; }
     double d;
     int p;
-    bargmax<NT>(v, vi, d, p);
+    bargmax<NT>(v, vi, d, p, amv, ami, 0);
     const int di = NT / nn, dj = NT - (NT / nn) * nn;
     for (int k = 0; k < nn; ++k) {
       if (!(d > thr) || !(tr > 0)) break;
@@ -583,7 +588,7 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
       }
       flops += 8.0 * (double)(nn - k - 1) * (nn - k - 1);
       r = k + 1;
-      bargmax<NT>(v, vi, d, p);
+      bargmax<NT>(v, vi, d, p, amv, ami, (k + 1) & 1);
     }
   }
   // 2. one-sided Jacobi on the rows piv[0..r)
