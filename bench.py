@@ -204,15 +204,23 @@ def main():
     ops = stn.prepare(circ, dev)
     rounds = split_rounds(ops)
     schedule = {"layer_mode": args.layer_mode, "layer_threads": args.layer_threads, "tuned": False}
-    if args.layer_mode == 0 and args.layer_threads == 0 and not args.no_tune:
+    W, K = args.warmup, args.steps
+    if args.layer_mode == 0 and args.layer_threads == 0 and not args.no_tune and W + K <= len(rounds):
         from paper_2605_29514_amd import tune
+        # tuning window: the first two crosstalk layers of the second timed
+        # round when several are timed (saturated rounds cost the most), else
+        # of the timed round; reached once, restored from a checkpoint per
+        # candidate when that fits in memory
+        r0 = W + 1 if K >= 2 else W
+        start = rounds[r0][0]
+        if start > 0 and sim.lib.stn_checkpoint_bytes(sim.ctx) > (16 << 30):
+            start = 0
         key = tune.problem_key(torch.cuda.get_device_name(0), circ.n, circ.n_shots, chi, prec, args.config)
-        t = tune.autotune(sim, ops, tune.layers_stop(ops, 2), key=key,
+        t = tune.autotune(sim, ops, tune.layers_stop(ops, 2, start), start=start, key=f"{key}|window@{start}",
                           log=lambda m: print("# " + m, file=sys.stderr, flush=True))
         schedule = {"layer_mode": t["choice"][0], "layer_threads": t["choice"][1], "tuned": True,
-                    "cached": t["cached"], "candidates_ms": t["ms"]}
+                    "cached": t["cached"], "candidates_ms": t["ms"], "tuning_window_ops": [start, tune.layers_stop(ops, 2, start)]}
         print(f"# autotuned schedule {t['choice']}", file=sys.stderr, flush=True)
-    W, K = args.warmup, args.steps
     if W + K > len(rounds):
         print(f"warmup + steps exceeds the {len(rounds)} rounds of the circuit", file=sys.stderr)
         sys.exit(2)

@@ -5,10 +5,14 @@ kernels with many blocks per product, or the fused per-shot layer kernel --
 and three block sizes for the fused kernel (64, 128, 256 threads per shot).
 Which one is fastest depends on the shot count, the bond dimensions the
 circuit reaches and the precision, so it is measured, not guessed: each
-candidate runs the same prefix of the real workload on the real Simulator
-(state reset before and after with stn_reset, so no second workspace is
-needed), timed with HIP events on the Simulator's stream, and the fastest is
-kept.  Results are cached per (device, problem) key in a JSON file.
+candidate runs the same window of the real workload on the real Simulator,
+timed with HIP events on the Simulator's stream, and the fastest is kept.
+The window starts either at the initial state (stn_reset before and after,
+no second workspace) or at a later point of the circuit -- the bonds of a
+saturated round differ from those of the first one -- reached once and
+restored for every candidate from a checkpoint (stn_checkpoint_save /
+stn_checkpoint_load).  Results are cached per (device, problem) key in a
+JSON file.
 
 All candidates compute the same results up to rounding order (the GPU parity
 tests run every one of them against the oracle).
@@ -66,11 +70,12 @@ def apply(sim, choice: Sequence[int]) -> None:
         sim.set_layer_threads(threads)
 
 
-def autotune(sim, ops, stop: int, *, key: Optional[str] = None, candidates: Iterable = CANDIDATES,
+def autotune(sim, ops, stop: int, *, start: int = 0, key: Optional[str] = None, candidates: Iterable = CANDIDATES,
              use_cache: bool = True, log=None) -> dict:
-    """Times ops[:stop] (a prefix of the workload, from the initial state) for
-    every candidate on `sim`, leaves `sim` reset to the initial state with the
-    fastest candidate applied, and returns {"choice", "ms", "cached"}."""
+    """Times ops[start:stop] for every candidate on `sim` (ops[:start] run
+    once beforehand, the state there restored for each candidate from a
+    checkpoint), leaves `sim` reset to the initial state with the fastest
+    candidate applied, and returns {"choice", "ms", "cached"}."""
     import torch
     from . import stn
     if use_cache and key:
@@ -79,20 +84,30 @@ def autotune(sim, ops, stop: int, *, key: Optional[str] = None, candidates: Iter
             apply(sim, hit["choice"])
             sim.reset()
             return {"choice": tuple(hit["choice"]), "ms": hit.get("ms"), "cached": True}
+    ck = None
+    if start > 0:
+        sim.reset()
+        stn.run_prepared(sim, ops, 0, start)
+        sim.sync()
+        ck = sim.checkpoint_save()
     timings: Dict[Tuple[int, int], float] = {}
     for cand in candidates:
         cand = tuple(cand)
         apply(sim, cand)
-        sim.reset()
+        if ck is None:
+            sim.reset()
+        else:
+            sim.checkpoint_load(ck)
         sim.sync()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(sim.stream)
-        stn.run_prepared(sim, ops, 0, stop)
+        stn.run_prepared(sim, ops, start, stop)
         b.record(sim.stream)
         sim.sync()
         timings[cand] = a.elapsed_time(b)
         if log:
             log(f"autotune {cand}: {timings[cand]:.1f} ms")
+    del ck
     best = pick(timings)
     apply(sim, best)
     sim.reset()
@@ -103,11 +118,13 @@ def autotune(sim, ops, stop: int, *, key: Optional[str] = None, candidates: Iter
     return {"choice": best, "ms": ms, "cached": False}
 
 
-def layers_stop(ops, layers: int = 2) -> int:
-    """Index just past the `layers`-th rotation op of a prepared op list (the
-    autotuning prefix: the first crosstalk layers)."""
+def layers_stop(ops, layers: int = 2, start: int = 0) -> int:
+    """Index just past the `layers`-th rotation op of a prepared op list at or
+    after `start` (the end of an autotuning window of crosstalk layers)."""
     seen = 0
     for i, op in enumerate(ops):
+        if i < start:
+            continue
         if op[0] == "rotate":
             seen += 1
             if seen == layers:

@@ -31,6 +31,7 @@ def test_layers_stop():
     assert tune.layers_stop(ops, 1) == 2
     assert tune.layers_stop(ops, 2) == 4
     assert tune.layers_stop(ops, 3) == 5
+    assert tune.layers_stop(ops, 1, start=2) == 4       # counted from the window start
 
 
 @pytest.mark.gpu
@@ -51,3 +52,11 @@ def test_autotune_leaves_initial_state(tmp_path, monkeypatch):
     assert np.array_equal(got["prob"], ref["prob"])
     again = tune.autotune(sim, ops, tune.layers_stop(ops, 2), key="k")
     assert again["cached"] and again["choice"] == r["choice"]
+    # a window inside the second round, reached once and restored per candidate
+    start = next(i for i, op in enumerate(ops) if op[0] == "measure") + 1
+    w = tune.autotune(sim, ops, tune.layers_stop(ops, 2, start), start=start, key="k2")
+    assert w["choice"] in tune.CANDIDATES and not w["cached"]
+    got = stn.run_circuit(circ, 8, "fp64", sim=sim)
+    ref = stn.run_circuit(circ, 8, "fp64", layer_mode=w["choice"][0], layer_threads=w["choice"][1])
+    assert np.array_equal(got["records"], ref["records"])
+    assert np.array_equal(got["prob"], ref["prob"])
