@@ -231,8 +231,11 @@ def main():
         sim.sync()
         print(f"# warmup round {r + 1}: {time.perf_counter() - t:.2f} s, max bond "
               f"{int(sim.bonds().max())}", file=sys.stderr, flush=True)
-    # dominant-class timing: all classes when asked, else the expected heaviest
-    sim.profile(None if args.profile_all else ["eigen", "qr", "gemm", "gram", "layer"])
+    # Timed region: launch events per kernel class only.  The device work
+    # counters (atomics from every block, per-phase clocks) slow the kernels
+    # they count, so the work per launch comes from a counted replay below.
+    prof_classes = None if args.profile_all else ["eigen", "qr", "gemm", "gram", "layer"]
+    sim.profile(prof_classes, counters=False)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -254,11 +257,30 @@ def main():
     ms = ev0.elapsed_time(ev1)
     sim.sync()
     prof = sim.profile_read()
-    phases = sim.profile_phases()
     lo, hi = rounds[W][0], rounds[W + K - 1][1]
     n_rot = rotations_in(ops, lo, hi) * circ.n_shots
     bonds = sim.bonds()
     value = n_rot / (ms / 1e3)
+    # counted replay of the same rounds from the initial state (deterministic:
+    # same launches, same bonds): algorithmic work per class, phase shares
+    sim.profile([])
+    sim.reset()
+    for r in range(W):
+        stn.run_prepared(sim, ops, *rounds[r])
+    sim.profile(prof_classes, counters=True)
+    for r in range(W, W + K):
+        stn.run_prepared(sim, ops, *rounds[r])
+        sim.sync()
+        print(f"# counted replay of round {r + 1} done", file=sys.stderr, flush=True)
+    work = sim.profile_read()
+    phases = sim.profile_phases()
+    sim.profile([])
+    for c in stn.K_CLASSES:
+        prof[c]["flops"], prof[c]["bytes"] = work[c]["flops"], work[c]["bytes"]
+        if work[c]["launches"] != prof[c]["launches"]:
+            print(f"# warning: class {c}: {prof[c]['launches']} timed launches, {work[c]['launches']} counted",
+                  file=sys.stderr, flush=True)
+    prof["layer_fp64_flops"], prof["eigen_sweeps"] = work["layer_fp64_flops"], work["eigen_sweeps"]
     # dominant kernel class by measured time
     classes = [c for c in stn.K_CLASSES if prof[c]["launches"] > 0]
     dom = max(classes, key=lambda c: prof[c]["ms"]) if classes else None

@@ -247,8 +247,14 @@ enum { STN_K_TABLEAU = 0,  /* tableau gates, rewrite, frame change */
 /* Diagnostic profiling.  Bit k of class_mask times every later launch of
  * kernel class k with HIP events on the context stream and enables the
  * device counters of algorithmic work (flops and bytes per launch, from the
- * realised bond dimensions).  class_mask = 0 switches it off.  Resets all
- * counters; synchronises. */
+ * realised bond dimensions, and the per-phase clocks of the fused kernel).
+ * With STN_PROFILE_TIMING_ONLY set in class_mask only the events are
+ * recorded: the counters are atomics from every block and slow the kernels
+ * they count, so timings meant to stand for the kernels' speed use this
+ * flag and take the work counts from a separate counted run.
+ * class_mask = 0 switches profiling off.  Resets all counters;
+ * synchronises. */
+#define STN_PROFILE_TIMING_ONLY 0x80000000u
 stn_status stn_profile(stn_ctx *ctx, unsigned class_mask);
 
 /* Reads (and clears the event list of) the profile: per class the summed

@@ -862,11 +862,13 @@ stn_status stn_profile(stn_ctx *c, unsigned class_mask) {
   if (!c) return STN_EINVAL;
   stn_status s = sync_status(c);
   if (s != STN_OK) return s;
+  const bool counters = !(class_mask & STN_PROFILE_TIMING_ONLY);
+  class_mask &= ~STN_PROFILE_TIMING_ONLY;
   c->prof.mask = class_mask;
   c->prof.recs.clear();
   c->prof.used = 0;
   for (int k = 0; k < K_COUNT; ++k) { c->prof_ms[k] = 0; c->prof_launches[k] = 0; }
-  c->mps.prof = class_mask ? 1 : 0;
+  c->mps.prof = (class_mask && counters) ? 1 : 0;
   hipError_t e = hipMemsetAsync(c->mps.work, 0, (size_t)kWorkWords * 8, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));

@@ -420,7 +420,10 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
   c = l;
 }
 
-template <typename T, int NT>
+// COUNT marks the launches made while the device work counters are on (a
+// separate instantiation, so timings and profiler traces of the two kinds
+// of launch never mix); the counting itself is switched by m.prof.
+template <typename T, int NT, bool COUNT>
 __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, const uint64_t *psgn,
                                               int W, int SW, const double *theta, int64_t stride,
                                               RotLayer L, int eig_n) {
@@ -452,7 +455,7 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
 // log P, then the projection as a two-term step (coefficients (1/2,
 // s sigma / 2) without a pivot, (1, s sigma) with one) and the outcome bit
 // masks (atomic OR into words cleared beforehand) for the frame update.
-template <typename T, int NT>
+template <typename T, int NT, bool COUNT>
 __global__ void __launch_bounds__(NT) k_meas(MpsDev m, const uint64_t *snap_sign, const c64 *ops, const c64 *eops,
                                              MeasStep a, const double *u, const uint8_t *forced, uint8_t *out,
                                              double *prob, uint64_t *negmask, uint64_t *mmask, int eig_n) {
@@ -537,8 +540,12 @@ template <typename T, int NT>
 void launch_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
                   const double *d_theta, int64_t stride, const RotLayer &L, hipStream_t st) {
   const int en = eig_lds_order(m.chi);
-  KLAUNCH(K_LAYER, (k_layer<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_pbits, d_psgn, W, SW,
-          d_theta, stride, L, en);
+  if (m.prof)
+    KLAUNCH(K_LAYER, (k_layer<T, NT, true>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_pbits,
+            d_psgn, W, SW, d_theta, stride, L, en);
+  else
+    KLAUNCH(K_LAYER, (k_layer<T, NT, false>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_pbits,
+            d_psgn, W, SW, d_theta, stride, L, en);
 }
 
 }  // namespace
@@ -554,8 +561,12 @@ void launch_meas(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *d_ops,
                  const MeasStep &a, const double *d_u, const uint8_t *d_forced, uint8_t *d_out, double *d_prob,
                  uint64_t *d_negmask, uint64_t *d_mmask, hipStream_t st) {
   const int en = eig_lds_order(m.chi);
-  KLAUNCH(K_EXPECT, (k_meas<T, NT>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_snap_sign, d_ops, d_eops, a, d_u,
-          d_forced, d_out, d_prob, d_negmask, d_mmask, en);
+  if (m.prof)
+    KLAUNCH(K_EXPECT, (k_meas<T, NT, true>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_snap_sign,
+            d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, en);
+  else
+    KLAUNCH(K_EXPECT, (k_meas<T, NT, false>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_snap_sign,
+            d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, en);
 }
 
 template <typename T>
@@ -580,12 +591,16 @@ void mps_rot_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_p
 template <typename T>
 hipError_t layer_prepare() {
   hipError_t e = hipSuccess;
-  const void *fs[6] = {(const void *)k_layer<T, 64>, (const void *)k_layer<T, 128>, (const void *)k_layer<T, 256>,
-                       (const void *)k_meas<T, 64>, (const void *)k_meas<T, 128>, (const void *)k_meas<T, 256>};
+  const void *fs[12] = {(const void *)k_layer<T, 64, false>, (const void *)k_layer<T, 128, false>,
+                        (const void *)k_layer<T, 256, false>, (const void *)k_meas<T, 64, false>,
+                        (const void *)k_meas<T, 128, false>, (const void *)k_meas<T, 256, false>,
+                        (const void *)k_layer<T, 64, true>, (const void *)k_layer<T, 128, true>,
+                        (const void *)k_layer<T, 256, true>, (const void *)k_meas<T, 64, true>,
+                        (const void *)k_meas<T, 128, true>, (const void *)k_meas<T, 256, true>};
   const int nts[6] = {64, 128, 256, 64, 128, 256};
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < 12; ++i) {
     hipError_t e2 = hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds_bytes(nts[i], sizeof(T) == 8, kEigLdsMax));
+                                        (int)lds_bytes(nts[i % 6], sizeof(T) == 8, kEigLdsMax));
     if (e == hipSuccess) e = e2;
   }
   return e;

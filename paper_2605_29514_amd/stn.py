@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstn.so")
 
 STN_FP64, STN_FP32 = 0, 1
+PROFILE_TIMING_ONLY = 0x80000000          # include/stn.h STN_PROFILE_TIMING_ONLY
 GATE_KIND = {"H": 0, "S": 1, "SDG": 2, "X": 3, "Y": 4, "Z": 5, "CX": 6, "CY": 7, "CZ": 8}
 STATUS = {0: "STN_OK", -1: "STN_EINVAL", -2: "STN_ENOMEM", -3: "STN_EDEVICE",
           -4: "STN_EZEROPROB", -5: "STN_ENUMERIC", -6: "STN_ESTATE"}
@@ -341,13 +342,17 @@ class Simulator:
     def center(self) -> int:
         return self.lib.stn_center(self.ctx)
 
-    def profile(self, classes=None):
-        """Start profiling the named kernel classes (None: all; []: stop)."""
+    def profile(self, classes=None, counters: bool = True):
+        """Start profiling the named kernel classes (None: all; []: stop).
+        counters=False records only the launch events (the device work
+        counters slow the kernels they count)."""
         if classes is None:
             classes = K_CLASSES
         mask = 0
         for c in classes:
             mask |= 1 << K_CLASSES.index(c)
+        if mask and not counters:
+            mask |= PROFILE_TIMING_ONLY
         self._check(self.lib.stn_profile(self.ctx, mask))
 
     def profile_read(self) -> dict:
