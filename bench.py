@@ -17,8 +17,13 @@ are timed.
 
 Prints one JSON line.  value = (shots x rotations in the timed rounds) / time.
 roofline: the kernel class with the largest time in the timed region, its
-algorithmic work (counted on the device from the realised bond dimensions)
-over its own launch time (HIP events on the library stream).
+algorithmic work (counted on the device from the realised bond dimensions,
+in a replay of the same rounds: the counters slow the kernels they count)
+over its own launch time (HIP events on the library stream, timed pass).
+plain_fp64: the plain per-shot FP64 GPU form (per-step kernels, one shot at a
+time) of the same rounds on the first shots, with the batched records
+forced: its rotation rate and the largest relative difference of the batched
+FP32 probabilities from it.
 cpu_baseline: the FP64 oracle timed on the host cores over a bounded sample
 of the same rounds (see --cpu-seconds).
 """
@@ -135,6 +140,43 @@ def _oracle_worker(args):
     return done, busy
 
 
+def plain_fp64_form(circ, chi, rounds, W, K, batched, n, dev):
+    """The plain per-shot FP64 GPU form of the same rounds: per-step kernels,
+    one shot at a time, FP64 throughout, on the first n shots with the
+    batched run's records forced.  Returns its rotation rate over the timed
+    rounds and the largest relative difference of the batched FP32
+    probabilities (every measurement run so far) from it."""
+    import torch
+    from paper_2605_29514_amd import stn
+    rec = torch.cat([r[0] for r in batched], dim=1)[:n].cpu().numpy()
+    prob = torch.cat([r[1] for r in batched], dim=1)[:n].cpu().numpy()
+    full = np.zeros((n, circ.n_measurements), np.uint8)
+    full[:, :rec.shape[1]] = rec
+    ms_total, worst = 0.0, 0.0
+    for s in range(n):
+        c1 = circ.shot_slice(s, s + 1)
+        sim = stn.Simulator(c1.n, 1, chi, "fp64", None, dev, layer_mode=1)
+        ops1 = stn.prepare(c1, dev, forced=full[s:s + 1])
+        r1 = split_rounds(ops1)
+        res = []
+        for r in range(W):
+            stn.run_prepared(sim, ops1, *r1[r], records=res)
+        sim.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(sim.stream)
+        for r in range(W, W + K):
+            stn.run_prepared(sim, ops1, *r1[r], records=res)
+        b.record(sim.stream)
+        sim.sync()
+        ms_total += a.elapsed_time(b)
+        p64 = torch.cat([x[1] for x in res], dim=1).cpu().numpy()[0]
+        worst = max(worst, float(np.max(np.abs(prob[s, :p64.shape[0]] - p64) / p64)))
+        del sim
+        print(f"# plain FP64 form: shot {s + 1}/{n} done", file=sys.stderr, flush=True)
+    return {"ms": ms_total, "shots": n, "per_step_kernels": True, "precision": "fp64",
+            "max_rel_prob_diff_batched_fp32": worst}
+
+
 def cpu_baseline(name, circ, ops_bounds, t_lo_round, t_hi_round, chi, eps, budget, cores):
     """Oracle rotations/s over the same rounds: `cores` worker processes (BLAS
     1 thread each) take shots 0, 1, 2, ... round-robin and time the
@@ -171,6 +213,9 @@ def main():
     ap.add_argument("--layer-mode", type=int, default=0, help="0 automatic, 1 per-step kernels, 2 fused")
     ap.add_argument("--layer-threads", type=int, default=0, help="threads per shot of the fused kernel")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain per-shot FP64 GPU form (per-step kernels, one shot at a time)")
+    ap.add_argument("--plain-shots", type=int, default=8)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -225,9 +270,10 @@ def main():
         print(f"warmup + steps exceeds the {len(rounds)} rounds of the circuit", file=sys.stderr)
         sys.exit(2)
     torch.cuda.synchronize()
+    batched = []                      # (outcomes, prob) device tensors of every measurement op run
     for r in range(W):
         t = time.perf_counter()
-        stn.run_prepared(sim, ops, *rounds[r])
+        stn.run_prepared(sim, ops, *rounds[r], records=batched)
         sim.sync()
         print(f"# warmup round {r + 1}: {time.perf_counter() - t:.2f} s, max bond "
               f"{int(sim.bonds().max())}", file=sys.stderr, flush=True)
@@ -242,7 +288,7 @@ def main():
     ev0.record(sim.stream)
     round_ev = []
     for r in range(W, W + K):
-        stn.run_prepared(sim, ops, *rounds[r])
+        stn.run_prepared(sim, ops, *rounds[r], records=batched)
         round_ev.append(torch.cuda.Event())
         round_ev[-1].record(sim.stream)
     ev1.record(sim.stream)
@@ -310,6 +356,12 @@ def main():
                 "fp64_flops_share": (prof["layer_fp64_flops"] / d["flops"]) if dom == "layer" and d["flops"] else None,
                 "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
                 "share_of_step_time": d["ms"] / ms if ms > 0 else None}
+    plain = None
+    if not args.no_plain and prec == "fp32":
+        plain = plain_fp64_form(circ, chi, rounds, W, K, batched, min(args.plain_shots, circ.n_shots), dev)
+        plain["value"] = plain["shots"] * (n_rot / circ.n_shots) / (plain.pop("ms") / 1e3)
+        plain["unit"] = "rotations/s"
+        plain["batched_fp32_speedup"] = value / plain["value"]
     cpu = None
     if not args.no_cpu:
         cores = min(os.cpu_count() or 1, 16)
@@ -331,6 +383,7 @@ def main():
                    "layer_phase_share": ({k: v / sum(phases.values()) for k, v in phases.items()}
                                          if sum(phases.values()) > 0 else None)},
         "roofline": roof,
+        "plain_fp64": plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
