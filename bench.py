@@ -22,8 +22,8 @@ in a replay of the same rounds: the counters slow the kernels they count)
 over its own launch time (HIP events on the library stream, timed pass).
 plain_fp64: the plain per-shot FP64 GPU form (per-step kernels, one shot at a
 time) of the same rounds on the first shots, with the batched records
-forced: its rotation rate and the largest relative difference of the batched
-FP32 probabilities from it.
+forced, within a time budget (--plain-seconds): its rotation rate and the
+largest relative difference of the batched FP32 probabilities from it.
 cpu_baseline: the FP64 oracle timed on the host cores over a bounded sample
 of the same rounds (see --cpu-seconds).
 """
@@ -140,40 +140,47 @@ def _oracle_worker(args):
     return done, busy
 
 
-def plain_fp64_form(circ, chi, rounds, W, K, batched, n, dev):
+def plain_fp64_form(circ, chi, rounds, W, K, batched, n, dev, budget_s):
     """The plain per-shot FP64 GPU form of the same rounds: per-step kernels,
-    one shot at a time, FP64 throughout, on the first n shots with the
-    batched run's records forced.  Returns its rotation rate over the timed
-    rounds and the largest relative difference of the batched FP32
-    probabilities (every measurement run so far) from it."""
+    one shot at a time, FP64 throughout, on up to the first n shots with the
+    batched run's records forced, until budget_s seconds are spent (at least
+    one timed round).  Returns its rotation rate over the timed rounds it ran
+    and the largest relative difference of the batched FP32 probabilities
+    from it over the measurements it ran."""
     import torch
     from paper_2605_29514_amd import stn
     rec = torch.cat([r[0] for r in batched], dim=1)[:n].cpu().numpy()
     prob = torch.cat([r[1] for r in batched], dim=1)[:n].cpu().numpy()
     full = np.zeros((n, circ.n_measurements), np.uint8)
     full[:, :rec.shape[1]] = rec
-    ms_total, worst = 0.0, 0.0
+    ms_total, rot_total, worst, shots_used = 0.0, 0, 0.0, 0
+    t_start = time.perf_counter()
     for s in range(n):
         c1 = circ.shot_slice(s, s + 1)
         sim = stn.Simulator(c1.n, 1, chi, "fp64", None, dev, layer_mode=1)
         ops1 = stn.prepare(c1, dev, forced=full[s:s + 1])
         r1 = split_rounds(ops1)
         res = []
-        for r in range(W):
+        for r in range(W + K):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(sim.stream)
             stn.run_prepared(sim, ops1, *r1[r], records=res)
-        sim.sync()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(sim.stream)
-        for r in range(W, W + K):
-            stn.run_prepared(sim, ops1, *r1[r], records=res)
-        b.record(sim.stream)
-        sim.sync()
-        ms_total += a.elapsed_time(b)
+            b.record(sim.stream)
+            sim.sync()
+            if r >= W:
+                ms_total += a.elapsed_time(b)
+                rot_total += rotations_in(ops1, *r1[r])
+            print(f"# plain FP64 form: shot {s + 1}, round {r + 1} done", file=sys.stderr, flush=True)
+            if r >= W and time.perf_counter() - t_start > budget_s:
+                break
         p64 = torch.cat([x[1] for x in res], dim=1).cpu().numpy()[0]
         worst = max(worst, float(np.max(np.abs(prob[s, :p64.shape[0]] - p64) / p64)))
+        shots_used += 1
         del sim
-        print(f"# plain FP64 form: shot {s + 1}/{n} done", file=sys.stderr, flush=True)
-    return {"ms": ms_total, "shots": n, "per_step_kernels": True, "precision": "fp64",
+        if time.perf_counter() - t_start > budget_s:
+            break
+    return {"value": rot_total / (ms_total / 1e3), "unit": "rotations/s", "shots": shots_used,
+            "timed_rotations": rot_total, "per_step_kernels": True, "precision": "fp64",
             "max_rel_prob_diff_batched_fp32": worst}
 
 
@@ -216,6 +223,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-shot FP64 GPU form (per-step kernels, one shot at a time)")
     ap.add_argument("--plain-shots", type=int, default=8)
+    ap.add_argument("--plain-seconds", type=float, default=60.0,
+                    help="time budget of the plain FP64 form (whole rounds; at least one)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -358,9 +367,8 @@ def main():
                 "share_of_step_time": d["ms"] / ms if ms > 0 else None}
     plain = None
     if not args.no_plain and prec == "fp32":
-        plain = plain_fp64_form(circ, chi, rounds, W, K, batched, min(args.plain_shots, circ.n_shots), dev)
-        plain["value"] = plain["shots"] * (n_rot / circ.n_shots) / (plain.pop("ms") / 1e3)
-        plain["unit"] = "rotations/s"
+        plain = plain_fp64_form(circ, chi, rounds, W, K, batched, min(args.plain_shots, circ.n_shots), dev,
+                                args.plain_seconds)
         plain["batched_fp32_speedup"] = value / plain["value"]
     cpu = None
     if not args.no_cpu:

@@ -502,9 +502,9 @@ __device__ void bargmax(double v, int i, double &vo, int &io, double *rv, int *r
 // well below its order.
 //
 //  1. Pivoted Cholesky, right-looking and in place: at step k the largest
-//     remaining diagonal d of the Schur complement picks the pivot p, row p
-//     becomes R_k = S_p / sqrt(d) (zero at the columns pivoted before) and
-//     the Schur complement of the other indices loses R_k^H R_k.  It stops
+//     remaining diagonal d of the Schur complement S picks the pivot p, the
+//     Schur complement of the other indices loses S_p^H S_p / d, and row p
+//     becomes R_k = S_p / sqrt(d) (zero at the columns pivoted before).  It stops
 //     once d <= chol_tol tr G; the part not captured has eigenvalues at most
 //     (nn - r) chol_tol tr G.  Then G = R^H R with the r rows of R in rows
 //     piv[0..r) of G.
@@ -546,43 +546,39 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
   if (tid == 0 && (!(tr == tr) || isinf(tr))) atomicOr(err, STN_ERR_NUMERIC);
   const double thr = chol_tol * tr;
   double flops = 0;
-  // 1. pivoted Cholesky
+  // 1. pivoted Cholesky.  The Schur updates use the raw pivot row S_p scaled
+  // by 1/d (no separate pass to publish the normalised row, so one barrier
+  // per pivot, inside bargmax); pos[j] = the step that pivoted j (nn: not
+  // yet).  The rows are normalised, and zeroed at the columns pivoted
+  // before them, in one pass after the loop.
   int r = 0;
   {
     double v = -INFINITY;
     int vi = 0x7fffffff;
-    for (int i = tid; i < nn; i += NT)
+    for (int i = tid; i < nn; i += NT) {
+      pos[i] = nn;
       if (dg[i] > v) { v = dg[i]; vi = i; }
+    }
     double d;
     int p;
     bargmax<NT>(v, vi, d, p, amv, ami, 0);
     const int di = NT / nn, dj = NT - (NT / nn) * nn;
     for (int k = 0; k < nn; ++k) {
       if (!(d > thr) || !(tr > 0)) break;
-      const double sd = sqrt(d), is = 1.0 / sd;
-      for (int j = tid; j < nn; j += NT) {
-        c64 x;
-        if (j == p) x = mk<double>(sd, 0);
-        else if (dg[j] == -INFINITY) x = mk<double>(0, 0);
-        else x = is * G[(size_t)p * ld + j];
-        G[(size_t)p * ld + j] = x;
-      }
-      if (tid == 0) piv[k] = p;
-      __syncthreads();
+      const double id = 1.0 / d;
+      if (tid == 0) { piv[k] = p; pos[p] = k; }
       const c64 *R = G + (size_t)p * ld;
       int i = tid / nn, j = tid - (tid / nn) * nn;
       for (int e = tid; e < nn * nn; e += NT, i += di, j += dj) {
         if (j >= nn) { j -= nn; ++i; }
-        if (i == p || j == p || i == j || dg[i] == -INFINITY || dg[j] == -INFINITY) continue;
-        G[(size_t)i * ld + j] = G[(size_t)i * ld + j] - cj(R[i]) * R[j];
+        if (i == p || j == p || i == j || pos[i] < nn || pos[j] < nn) continue;
+        G[(size_t)i * ld + j] = G[(size_t)i * ld + j] - id * (cj(R[i]) * R[j]);
       }
       v = -INFINITY;
       vi = 0x7fffffff;
       for (int q = tid; q < nn; q += NT) {
-        if (q == p) { dg[q] = -INFINITY; continue; }
-        const double dq = dg[q];
-        if (dq == -INFINITY) continue;
-        const double nd = dq - norm2(R[q]);
+        if (q == p || pos[q] < nn) continue;
+        const double nd = dg[q] - id * norm2(R[q]);
         dg[q] = nd;
         if (nd > v) { v = nd; vi = q; }
       }
@@ -590,6 +586,18 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
       r = k + 1;
       bargmax<NT>(v, vi, d, p, amv, ami, (k + 1) & 1);
     }
+    // row k of R: sqrt(d_k) at its pivot, 0 at columns pivoted before step
+    // k, S_pk / sqrt(d_k) elsewhere (dg[p_k] still holds d_k)
+    for (int e = tid; e < r * nn; e += NT) {
+      const int kk = e / nn, jj = e - kk * nn;
+      const int pk = piv[kk];
+      const double dk = dg[pk];
+      c64 *row = G + (size_t)pk * ld;
+      if (jj == pk) row[jj] = mk<double>(sqrt(dk), 0);
+      else if (pos[jj] < kk) row[jj] = mk<double>(0, 0);
+      else row[jj] = (1.0 / sqrt(dk)) * row[jj];
+    }
+    __syncthreads();
   }
   // 2. one-sided Jacobi on the rows piv[0..r)
   int sweeps = 0;
