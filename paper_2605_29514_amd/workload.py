@@ -263,7 +263,7 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
                    theta_law: str = "fixed", theta_range=(0.02, 0.10),
                    p: float = 0.0, per_layer_params: bool = False,
                    random_sign: bool = False, final_readout: bool = True,
-                   dense_noise: bool = False) -> Circuit:
+                   dense_noise: bool = False, crosstalk: str = "coherent") -> Circuit:
     """Memory-Z experiment on the rotated code with ZZ(Z) crosstalk.
 
     dense_noise: emit a noise op at every noise location even when no shot
@@ -279,7 +279,15 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
       its own angle parameter index (used for gradients).
     random_sign: each rotation instance and shot flips the sign of its angle
       with probability 1/2 (Eq. 9).
+    crosstalk:
+      "coherent"  rotations exp(-i theta Z..Z) (Eq. 4)
+      "pta"       their Pauli-twirled approximation (Eq. 6): each coupling
+                  and shot applies Z..Z with probability sin^2(theta), drawn
+                  from its own stream, as a Pauli noise op (no rotation, so
+                  the run is Clifford-only)
     """
+    if crosstalk not in ("coherent", "pta"):
+        raise ValueError(crosstalk)
     lay = rotated_layout(d)
     n = lay.n
     S = n_shots
@@ -311,6 +319,7 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
     else:
         raise ValueError(theta_law)
     g_sign = _rng(seed, 4)
+    g_pta = _rng(seed, 5)
     noise = _Noise(seed, S, n, p)
     g_meas = _rng(seed, 3)
     ops = []
@@ -335,6 +344,15 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
                 if random_sign:
                     flip = _uniform53(g_sign, (S, R)) < 0.5
                     th = np.where(flip, -th, th)
+                if crosstalk == "pta":
+                    fire = _uniform53(g_pta, (S, R)) < np.sin(th) ** 2
+                    z = np.zeros((S, n), dtype=bool)
+                    for c in range(R):
+                        for q in paulis[c]:
+                            if q >= 0:
+                                z[:, q] ^= fire[:, c]
+                    add_noise((np.zeros((S, n), dtype=bool), z))
+                    continue
                 if per_layer_params:
                     param = np.arange(n_params, n_params + R, dtype=np.int32)
                     n_params += R
@@ -353,7 +371,7 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
         add_noise(noise.x_flip(lay.data, 5 * p))
         ops.append({"op": "measure", "qubits": np.array(lay.data, np.int32), "reset": False,
                     "u": _uniform53(g_meas, (S, len(lay.data)))})
-    meta = {"d": d, "rounds": rounds, "p": p, "theta_law": theta_law,
+    meta = {"d": d, "rounds": rounds, "p": p, "theta_law": theta_law, "crosstalk": crosstalk,
             "n_nn": len(nn), "n_nnn": len(nnn), "n_tri": len(tri)}
     return Circuit(n, S, ops, lay, n_params, meta)
 

@@ -244,3 +244,20 @@ def test_repeat_is_bit_identical(B, mode):
     for s in (0, 7):
         for j in range(circ.n):
             assert np.array_equal(a["sim"].site(s, j), b["sim"].site(s, j))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_random_sign_crosstalk(B, prec):
+    """Random-sign coherent crosstalk (Eq. 9): per-shot, per-instance angle signs."""
+    circ = W.memory_circuit(3, 2, 6, seed=51, theta_nn=0.08, nnn=True, random_sign=True, p=0.01)
+    run_parity(B, circ, 16, prec, range(6))
+
+
+def test_pta_crosstalk_is_clifford(B):
+    """Pauli-twirled crosstalk (Eq. 6) is a Pauli noise model: records and
+    tableau match the oracle bit for bit and the MPS never leaves bond 1."""
+    circ = W.memory_circuit(3, 2, 32, seed=61, theta_nn=0.2, nnn=True, p=0.01, crosstalk="pta")
+    run_parity(B, circ, 4, "fp64", range(0, 32, 4))
+    g = B.run_circuit(circ, 4, "fp32")
+    assert np.all(g["sim"].bonds() == 1)
+    assert np.all(np.isin(np.round(g["prob"], 12), [0.5, 1.0]))
