@@ -238,7 +238,8 @@ enum { STN_K_TABLEAU = 0,  /* tableau gates, rewrite, frame change */
        STN_K_QR = 2,       /* Householder QR of the compression sweeps and centre moves */
        STN_K_GEMM = 3,     /* site-pair contractions (R absorb, X V, Q N) */
        STN_K_GRAM = 4,     /* FP64 Gram X^H X of the truncation */
-       STN_K_EIGEN = 5,    /* FP64 Hermitian eigen-solve of the Gram */
+       STN_K_EIGEN = 5,    /* FP64 eigen-solve of the Gram (FP32 path: pivoted Cholesky +
+                              one-sided Jacobi; FP64 path: two-sided Jacobi) */
        STN_K_SELECT = 6,   /* truncation selection, FP64 renormalisation */
        STN_K_EXPECT = 7,   /* measurement transfer matrices and outcomes */
        STN_K_LAYER = 8,    /* fused per-shot rotation-layer kernel (all of its work) */
@@ -260,8 +261,10 @@ stn_status stn_profile(stn_ctx *ctx, unsigned class_mask);
 /* Reads (and clears the event list of) the profile: per class the summed
  * kernel milliseconds, algorithmic flops and bytes, and the number of timed
  * launches (arrays of STN_K_COUNT entries, any may be NULL), the total number
- * of Jacobi sweeps executed, and the FP64 part (Gram + eigen-solve) of the
- * STN_K_LAYER flops.  Synchronises. */
+ * of eigen-solve sweeps executed (two-sided Jacobi sweeps on the FP64 path,
+ * one-sided on the FP32 path), and the FP64 part (Gram + eigen-solve) of the
+ * STN_K_LAYER flops.  Work counts, sweeps and phases stay zero in
+ * STN_PROFILE_TIMING_ONLY mode.  Synchronises. */
 stn_status stn_profile_read(stn_ctx *ctx, double *host_ms, double *host_flops,
                             double *host_bytes, long long *host_launches,
                             double *host_eig_sweeps, double *host_layer_fp64_flops);
@@ -269,9 +272,11 @@ stn_status stn_profile_read(stn_ctx *ctx, double *host_ms, double *host_flops,
 /* Phases of the fused layer kernel, summed over shots in shader clock
  * cycles while profiling is on (stn_profile with any class): 0 angle and
  * single-site steps, 1 centre moves, 2 bond-2 blocks, 3 QR of the
- * left-to-right sweep, 4 its R absorption, 5 FP64 Gram, 6 Jacobi
- * eigen-solve, 7 selection, the two truncation products and the
- * renormalisation.  host_cycles: 8 doubles.  Synchronises. */
+ * left-to-right sweep (or the environment Grams), 4 its R absorption,
+ * 5 FP64 reduced density, 6 eigen-solve (FP32 path: pivoted Cholesky and
+ * one-sided Jacobi; FP64 path: two-sided Jacobi), 7 selection, the two
+ * truncation products and the renormalisation.  host_cycles: 8 doubles.
+ * Synchronises. */
 stn_status stn_profile_phases(stn_ctx *ctx, double *host_cycles);
 
 /* How stn_rotate schedules its kernels: 1 = one launch per kernel step for
