@@ -261,19 +261,22 @@ def main():
     W, K = args.warmup, args.steps
     if args.layer_mode == 0 and args.layer_threads == 0 and not args.no_tune and W + K <= len(rounds):
         from paper_2605_29514_amd import tune
-        # tuning window: the first two crosstalk layers of the second timed
-        # round when several are timed (saturated rounds cost the most), else
-        # of the timed round; reached once, restored from a checkpoint per
-        # candidate when that fits in memory
+        # tuning window: with one timed round, that whole round (its early
+        # layers, where bonds are small, favour other block sizes than the
+        # rest); with several, the first two crosstalk layers of the second
+        # timed round (saturated rounds cost the most, a whole one per
+        # candidate would take minutes).  Reached once, restored from a
+        # checkpoint per candidate when that fits in memory.
         r0 = W + 1 if K >= 2 else W
         start = rounds[r0][0]
         if start > 0 and sim.lib.stn_checkpoint_bytes(sim.ctx) > (16 << 30):
             start = 0
+        stop = rounds[r0][1] if K == 1 else tune.layers_stop(ops, 2, start)
         key = tune.problem_key(torch.cuda.get_device_name(0), circ.n, circ.n_shots, chi, prec, args.config)
-        t = tune.autotune(sim, ops, tune.layers_stop(ops, 2, start), start=start, key=f"{key}|window@{start}",
+        t = tune.autotune(sim, ops, stop, start=start, key=f"{key}|window@{start}:{stop}",
                           log=lambda m: print("# " + m, file=sys.stderr, flush=True))
         schedule = {"layer_mode": t["choice"][0], "layer_threads": t["choice"][1], "tuned": True,
-                    "cached": t["cached"], "candidates_ms": t["ms"], "tuning_window_ops": [start, tune.layers_stop(ops, 2, start)]}
+                    "cached": t["cached"], "candidates_ms": t["ms"], "tuning_window_ops": [start, stop]}
         print(f"# autotuned schedule {t['choice']}", file=sys.stderr, flush=True)
     if W + K > len(rounds):
         print(f"warmup + steps exceeds the {len(rounds)} rounds of the circuit", file=sys.stderr)

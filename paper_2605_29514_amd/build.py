@@ -32,6 +32,9 @@ def hipcc() -> str:
 def flags():
     return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # the fused kernels inline their whole per-shot step: out-of-line
+            # calls would turn LDS accesses generic (flat) and add call frames
+            "-mllvm", "-amdgpu-inline-max-bb=3000",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

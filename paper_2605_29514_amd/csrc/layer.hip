@@ -85,20 +85,25 @@ __device__ void blk_gemm(int M, int N, int K, const cplx<TA> *A, int lda, int op
   __syncthreads();
 }
 
+template <typename T>
+struct Pair {
+  cplx<T> a, b;
+};
+
 template <typename T, int NT>
 __device__ void blk_copy(cplx<T> *dst, const cplx<T> *src, int cnt) {
-  for (int e = threadIdx.x; e < cnt; e += NT) dst[e] = src[e];
+  blk_each<NT, 4, cplx<T>>(cnt, [&](int e) { return src[e]; }, [&](int e, cplx<T> v) { dst[e] = v; });
   __syncthreads();
 }
 
 // QR of the rows x cols matrix at A (global, may be overwritten): staged in
-// LDS when it fits.  Q -> Qd (qt as in qr_block), R -> Rd.
+// LDS when it fits.  Q -> Qd (qt as in qr_block), R -> Rd.  gvs/gvd are the
+// shot's global reflector buffers, used when rows exceed the LDS ones.
 template <typename T, int NT>
-__device__ void blk_qr(const MpsDev &m, int s, int rows, int cols, cplx<T> *A, cplx<T> *Qd, int qt,
+__device__ void blk_qr(c64 *gvs, double *gvd, int rows, int cols, cplx<T> *A, cplx<T> *Qd, int qt,
                        cplx<T> *Rd, char *lds) {
-  const Fallback f = fallback(m, s);
-  c64 *vs = rows <= kLdsQrRows ? reinterpret_cast<c64 *>(lds + kVs) : f.vs;
-  double *vd = rows <= kLdsQrRows ? reinterpret_cast<double *>(lds + kVd) : f.vd;
+  c64 *vs = rows <= kLdsQrRows ? reinterpret_cast<c64 *>(lds + kVs) : gvs;
+  double *vd = rows <= kLdsQrRows ? reinterpret_cast<double *>(lds + kVd) : gvd;
   c64 *wp = reinterpret_cast<c64 *>(lds + kWp);
   if ((size_t)rows * cols * sizeof(cplx<T>) <= kLdsQrMat) {
     cplx<T> *Al = reinterpret_cast<cplx<T> *>(lds + u_off(NT));
@@ -117,7 +122,7 @@ __device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds, int cls
   const int p = rows < cols ? rows : cols;
   cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
   blk_copy<T, NT>(X, slot<T>(m, c, s), rows * cols);
-  blk_qr<T, NT>(m, s, rows, cols, X, slot<T>(m, c, s), 0, R, lds);
+  blk_qr<T, NT>(fallback(m, s).vs, fallback(m, s).vd, rows, cols, X, slot<T>(m, c, s), 0, R, lds);
   blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, slot<T>(m, c + 1, s), N, 0, X, N, lds);
   if (threadIdx.x == 0) {
     b[c + 1] = p;
@@ -141,7 +146,7 @@ __device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds, int cls)
     X[(size_t)cc * dl + a] = cj(A[e]);
   }
   __syncthreads();
-  blk_qr<T, NT>(m, s, rows, cols, X, slot<T>(m, c, s), 1, R, lds);
+  blk_qr<T, NT>(fallback(m, s).vs, fallback(m, s).vd, rows, cols, X, slot<T>(m, c, s), 1, R, lds);
   blk_gemm<T, T, T, T, NT>(M, p, cols, slot<T>(m, c - 1, s), cols, 0, R, cols, 1, X, p, lds);
   if (threadIdx.x == 0) {
     b[c] = p;
@@ -253,29 +258,43 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     so.get(j, o1, o2);
     cplx<T> *out = (j == l && !env) ? scr<T>(m.T, m.T_cap, s) : wslot<T>(m, j, s);
     const cplx<T> *A = slot<T>(m, j, s);
-    for (int e = tid; e < Dl * Dr; e += NT) {
-      const int a = e / Dr, cc = e % Dr;
+    // branch of element (a, cc): 0 / 1 for the two terms of the MPO, -1 off
+    // the block diagonal
+    auto branch = [&](int a, int cc) {
       const int ba = a >= dl, bc = cc >= dr;
-      int br = -1;
-      if (j == l) br = bc;
-      else if (j == r) br = ba;
-      else if (ba == bc) br = ba;
-      c64 y0 = mk<double>(0, 0), y1 = mk<double>(0, 0);
-      if (br >= 0) {
-        const int aa = (j == l) ? a : a - (ba ? dl : 0);
-        const int c2 = (j == r) ? cc : cc - (bc ? dr : 0);
-        const c64 x0 = cvt<double>(A[(size_t)(aa * 2 + 0) * dr + c2]), x1 = cvt<double>(A[(size_t)(aa * 2 + 1) * dr + c2]);
-        // element-wise selects keep o1, o2 in registers (a pointer to either
-        // would put both arrays in scratch memory)
-        const c64 u0 = br ? o2[0] : o1[0], u1 = br ? o2[1] : o1[1];
-        const c64 u2 = br ? o2[2] : o1[2], u3 = br ? o2[3] : o1[3];
-        y0 = u0 * x0 + u1 * x1;
-        y1 = u2 * x0 + u3 * x1;
-        if (j == l) { const c64 k = br ? cb : ca; y0 = k * y0; y1 = k * y1; }
-      }
-      out[(size_t)(a * 2 + 0) * Dr + cc] = cvt<T>(y0);
-      out[(size_t)(a * 2 + 1) * Dr + cc] = cvt<T>(y1);
-    }
+      if (j == l) return bc;
+      if (j == r) return ba;
+      return ba == bc ? ba : -1;
+    };
+    blk_each_rc<NT, 4, Pair<T>>(
+        Dl, Dr,
+        [&](int a, int cc) {
+          const int br = branch(a, cc);
+          Pair<T> x{mk<T>(0, 0), mk<T>(0, 0)};
+          if (br >= 0) {
+            const int aa = (j == l) ? a : a - (br ? dl : 0);
+            const int c2 = (j == r) ? cc : cc - (br ? dr : 0);
+            x.a = A[(size_t)(aa * 2 + 0) * dr + c2];
+            x.b = A[(size_t)(aa * 2 + 1) * dr + c2];
+          }
+          return x;
+        },
+        [&](int a, int cc, Pair<T> x) {
+          const int br = branch(a, cc);
+          c64 y0 = mk<double>(0, 0), y1 = mk<double>(0, 0);
+          if (br >= 0) {
+            const c64 x0 = cvt<double>(x.a), x1 = cvt<double>(x.b);
+            // element-wise selects keep o1, o2 in registers (a pointer to
+            // either would put both arrays in scratch memory)
+            const c64 u0 = br ? o2[0] : o1[0], u1 = br ? o2[1] : o1[1];
+            const c64 u2 = br ? o2[2] : o1[2], u3 = br ? o2[3] : o1[3];
+            y0 = u0 * x0 + u1 * x1;
+            y1 = u2 * x0 + u3 * x1;
+            if (j == l) { const c64 k = br ? cb : ca; y0 = k * y0; y1 = k * y1; }
+          }
+          out[(size_t)(a * 2 + 0) * Dr + cc] = cvt<T>(y0);
+          out[(size_t)(a * 2 + 1) * Dr + cc] = cvt<T>(y1);
+        });
     if (tid == 0) { w[j] = Dl; if (j == r) w[r + 1] = dr; }
   }
   __syncthreads();
@@ -311,7 +330,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     const int rows = 2 * w[j], cols = w[j + 1], N = 2 * w[j + 2];
     const int p = rows < cols ? rows : cols;
     cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
-    blk_qr<T, NT>(m, s, rows, cols, X, wslot<T>(m, j, s), 0, R, lds);
+    blk_qr<T, NT>(fallback(m, s).vs, fallback(m, s).vd, rows, cols, X, wslot<T>(m, j, s), 0, R, lds);
     clk.lap(m, 3);
     blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, wslot<T>(m, j + 1, s), N, 0, X, N, lds);
     clk.lap(m, 4);
@@ -358,12 +377,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         if (nn <= kJacLdsN) {
           c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
           ldw = nn + 1;
-          int r0 = tid / nn, c0 = tid - (tid / nn) * nn;
-          const int dr0 = NT / nn, dc0 = NT - (NT / nn) * nn;
-          for (int e = tid; e < nn * nn; e += NT, r0 += dr0, c0 += dc0) {
-            if (c0 >= nn) { c0 -= nn; ++r0; }
-            Gl[r0 * ldw + c0] = Gg[e];
-          }
+          blk_each_rc<NT, 8, c64>(nn, nn, [&](int i, int j) { return Gg[i * nn + j]; },
+                                  [&](int i, int j, c64 v) { Gl[i * ldw + j] = v; });
           __syncthreads();
           Gw = Gl;
           Vw = Gl + kJacLdsN * (kJacLdsN + 1);
@@ -374,24 +389,25 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         Vsel = Gg;
       } else {
         // FP32 path: pivoted Cholesky + one-sided Jacobi on the factor
-        int *piv = li ? reinterpret_cast<int *>(lds + kPiv) : f.piv;
-        double *dg = li ? reinterpret_cast<double *>(lds + kDg) : f.dg;
-        c64 *Gw = Gg;
-        int ldw = nn;
-        if (nn <= eig_n) {                    // factor in LDS (rows padded by one)
+        const double ct = chol_tol(m.eps_cut, nn);
+        double *ev = m.ev + s * m.ev_cap;
+        c64 *V = m.V + s * m.V_cap;
+        if (nn <= eig_n) {
+          // factor (rows padded by one) and index tables all in LDS: a call
+          // of its own, so that every access in it is a direct LDS access
           c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
-          ldw = nn + 1;
-          int r0 = tid / nn, c0 = tid - (tid / nn) * nn;
-          const int dr0 = NT / nn, dc0 = NT - (NT / nn) * nn;
-          for (int e = tid; e < nn * nn; e += NT, r0 += dr0, c0 += dc0) {
-            if (c0 >= nn) { c0 -= nn; ++r0; }
-            Gl[r0 * ldw + c0] = Gg[e];
-          }
+          const int ldw = nn + 1;
+          blk_each_rc<NT, 8, c64>(nn, nn, [&](int i, int j) { return Gg[i * nn + j]; },
+                                  [&](int i, int j, c64 v) { Gl[i * ldw + j] = v; });
           __syncthreads();
-          Gw = Gl;
+          fe = eig_psd<NT>(nn, Gl, ldw, ev, V, m.err, reinterpret_cast<int *>(lds + kPiv),
+                           reinterpret_cast<int *>(lds + kPos), reinterpret_cast<double *>(lds + kDg), sweeps, ct,
+                           eig_conv_tol<T>(), eig_rot_tol<T>());
+        } else {
+          int *piv = li ? reinterpret_cast<int *>(lds + kPiv) : f.piv;
+          double *dg = li ? reinterpret_cast<double *>(lds + kDg) : f.dg;
+          fe = eig_psd<NT>(nn, Gg, nn, ev, V, m.err, piv, pos, dg, sweeps, ct, eig_conv_tol<T>(), eig_rot_tol<T>());
         }
-        fe = eig_psd<NT>(nn, Gw, ldw, m.ev + s * m.ev_cap, m.V + s * m.V_cap, m.err, piv, pos, dg, sweeps,
-                         chol_tol(m.eps_cut, nn), eig_conv_tol<T>(), eig_rot_tol<T>());
         Vsel = m.V + s * m.V_cap;
       }
       if (tid == 0) {
@@ -424,7 +440,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
 // separate instantiation, so timings and profiler traces of the two kinds
 // of launch never mix); the counting itself is switched by m.prof.
 template <typename T, int NT, bool COUNT>
-__global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, const uint64_t *psgn,
+__global__ void __launch_bounds__(NT, 2) k_layer(MpsDev m, const uint64_t *pbits, const uint64_t *psgn,
                                               int W, int SW, const double *theta, int64_t stride,
                                               RotLayer L, int eig_n) {
   extern __shared__ __align__(16) char lds[];
@@ -456,7 +472,7 @@ __global__ void __launch_bounds__(NT) k_layer(MpsDev m, const uint64_t *pbits, c
 // s sigma / 2) without a pivot, (1, s sigma) with one) and the outcome bit
 // masks (atomic OR into words cleared beforehand) for the frame update.
 template <typename T, int NT, bool COUNT>
-__global__ void __launch_bounds__(NT) k_meas(MpsDev m, const uint64_t *snap_sign, const c64 *ops, const c64 *eops,
+__global__ void __launch_bounds__(NT, 2) k_meas(MpsDev m, const uint64_t *snap_sign, const c64 *ops, const c64 *eops,
                                              MeasStep a, const double *u, const uint8_t *forced, uint8_t *out,
                                              double *prob, uint64_t *negmask, uint64_t *mmask, int eig_n) {
   extern __shared__ __align__(16) char lds[];

@@ -50,6 +50,58 @@ __device__ inline double qr_flops(double m, double n) {
   return 8.0 * (r + q);
 }
 
+// ------------------------------------------------------ element loops
+// Block loop over elements e in [0, n), NT apart, U per thread at a time:
+// the U loads ld(e) of a group are all issued before the first store
+// st(e, v), so they wait on memory together instead of one after another
+// (a plain loop cannot be reordered when the compiler cannot rule out
+// that a store aliases a later load).
+template <int NT, int U, typename V, typename LD, typename ST>
+__device__ __forceinline__ void blk_each(int n, LD ld, ST st) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * NT < n) v[u] = ld(e0 + u * NT);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * NT < n) st(e0 + u * NT, v[u]);
+  }
+}
+
+// The same over the elements of a rows x cols matrix in row-major order,
+// with their row and column stepped along (no division per element):
+// ld(i, j), st(i, j, v).
+template <int NT, int U, typename V, typename LD, typename ST>
+__device__ __forceinline__ void blk_each_rc(int rows, int cols, LD ld, ST st) {
+  if (cols <= 0) return;
+  const int di = NT / cols, dj = NT - di * cols;
+  int i0 = threadIdx.x / cols, j0 = threadIdx.x - i0 * cols;
+  auto step = [&](int &i, int &j) {
+    i += di;
+    j += dj;
+    if (j >= cols) { j -= cols; ++i; }
+  };
+  while (i0 < rows) {
+    V v[U];
+    int i = i0, j = j0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i < rows) v[u] = ld(i, j);
+      step(i, j);
+    }
+    i = i0;
+    j = j0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i < rows) st(i, j, v[u]);
+      step(i, j);
+    }
+    i0 = i;
+    j0 = j;
+  }
+}
+
 // ------------------------------------------------------------ reductions
 // Sum / max over the block; every thread receives the result.
 template <int NT, typename V>
@@ -110,19 +162,20 @@ template <> struct Mfma<float> {
   __device__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
-// Block tile of the matrix-core GEMM: one 16x16 block per wave, so a block
-// of NT threads covers TM x TN = (16 x 16) x (NT / 64) outputs.
+// Block tile of the matrix-core GEMM: each wave owns WB 16x16 blocks side
+// by side along N, so a block of NT threads covers TM x TN outputs with
+// TM x TN = (16 x 16 WB) x (NT / 64); TM, TN <= GT (the staging size).
 template <int NT> struct MTile;
-template <> struct MTile<64> { static constexpr int TM = 16, TN = 16; };
-template <> struct MTile<128> { static constexpr int TM = 32, TN = 16; };
-template <> struct MTile<256> { static constexpr int TM = 32, TN = 32; };
+template <> struct MTile<64> { static constexpr int TM = 16, TN = 32, WB = 2; };
+template <> struct MTile<128> { static constexpr int TM = 32, TN = 32, WB = 2; };
+template <> struct MTile<256> { static constexpr int TM = 32, TN = 32, WB = 1; };
 
 // One TM x TN tile of C = op(A) op(B) on the matrix cores.
 //   opA = 0: A is M x K (lda);  opA = 1: A is K x M and op(A) = A^H.
 //   opB = 0: B is K x N (ldb);  opB = 1: B is N x K and op(B) = B^H.
 // Operands are staged through LDS in ACC precision (GK columns at a time,
-// zero-padded past M, N, K); each wave owns one 16x16 block of the tile and
-// forms it as a complex product of four real MFMA chains:
+// zero-padded past M, N, K); each wave forms its 16x16 blocks as complex
+// products of four real MFMA chains each:
 // re += a_re b_re - a_im b_im, im += a_re b_im + a_im b_re.
 // stage: GemmStage<ACC>::bytes of LDS.
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
@@ -131,45 +184,70 @@ __device__ void gemm_tile(int M, int N, int K, const cplx<TA> *A, int lda, int o
                           int tn, void *stage) {
   using MF = Mfma<ACC>;
   using V = typename MF::V;
-  constexpr int TM = MTile<NT>::TM, TN = MTile<NT>::TN;
+  constexpr int TM = MTile<NT>::TM, TN = MTile<NT>::TN, WB = MTile<NT>::WB;
+  constexpr int WN = TN / (16 * WB);                               // waves along N
+  static_assert(TM <= GT && TN <= GT && (NT / 64) * 16 * 16 * WB == TM * TN, "GEMM tile");
   cplx<ACC> *As = reinterpret_cast<cplx<ACC> *>(stage);          // [TM][GK + 1]
   cplx<ACC> *Bs = As + GT * (GK + 1);                              // [GK][TN + 1]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row0 = tm * TM, col0 = tn * TN;
-  const int sm = (wave / (TN / 16)) * 16, sn = (wave % (TN / 16)) * 16;
-  V re, im;
-  for (int i = 0; i < 4; ++i) { re[i] = 0; im[i] = 0; }
+  const int sm = (wave / WN) * 16, sn = (wave % WN) * 16 * WB;
+  V re[WB], im[WB];
+#pragma unroll
+  for (int w = 0; w < WB; ++w)
+    for (int i = 0; i < 4; ++i) { re[w][i] = 0; im[w][i] = 0; }
+  // every operand element of a k-step is loaded before any is stored, so
+  // the loads of a step are in flight together
+  constexpr int NA = (TM * GK + NT - 1) / NT, NB = (TN * GK + NT - 1) / NT;
   for (int k0 = 0; k0 < K; k0 += GK) {
-    for (int e = tid; e < TM * GK; e += NT) {
-      int mi = e / GK, ki = e % GK;
-      int m = row0 + mi, k = k0 + ki;
-      cplx<ACC> v = mk<ACC>(0, 0);
-      if (m < M && k < K) v = opA ? cj(cvt<ACC>(A[(size_t)k * lda + m])) : cvt<ACC>(A[(size_t)m * lda + k]);
-      As[mi * (GK + 1) + ki] = v;
+    cplx<TA> ra[NA];
+    cplx<TB_> rb[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + i * NT, mi = e / GK, ki = e % GK;
+      const int m = row0 + mi, k = k0 + ki;
+      ra[i] = mk<TA>(0, 0);
+      if (e < TM * GK && m < M && k < K) ra[i] = opA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
     }
-    for (int e = tid; e < TN * GK; e += NT) {
-      int ki = e / TN, ni = e % TN;
-      int n = col0 + ni, k = k0 + ki;
-      cplx<ACC> v = mk<ACC>(0, 0);
-      if (n < N && k < K) v = opB ? cj(cvt<ACC>(B[(size_t)n * ldb + k])) : cvt<ACC>(B[(size_t)k * ldb + n]);
-      Bs[ki * (TN + 1) + ni] = v;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + i * NT, ki = e / TN, ni = e % TN;
+      const int n = col0 + ni, k = k0 + ki;
+      rb[i] = mk<TB_>(0, 0);
+      if (e < TN * GK && n < N && k < K) rb[i] = opB ? B[(size_t)n * ldb + k] : B[(size_t)k * ldb + n];
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + i * NT;
+      if (e < TM * GK) As[(e / GK) * (GK + 1) + e % GK] = opA ? cj(cvt<ACC>(ra[i])) : cvt<ACC>(ra[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + i * NT;
+      if (e < TN * GK) Bs[(e / TN) * (TN + 1) + e % TN] = opB ? cj(cvt<ACC>(rb[i])) : cvt<ACC>(rb[i]);
     }
     __syncthreads();
     const int kend = K - k0 < GK ? K - k0 : GK;
     for (int kk = 0; kk < kend; kk += 4) {
       const cplx<ACC> a = As[(sm + (lane & 15)) * (GK + 1) + kk + (lane >> 4)];
-      const cplx<ACC> b = Bs[(kk + (lane >> 4)) * (TN + 1) + sn + (lane & 15)];
-      re = MF::mma(a.x, b.x, re);
-      re = MF::mma(-a.y, b.y, re);
-      im = MF::mma(a.x, b.y, im);
-      im = MF::mma(a.y, b.x, im);
+#pragma unroll
+      for (int w = 0; w < WB; ++w) {
+        const cplx<ACC> b = Bs[(kk + (lane >> 4)) * (TN + 1) + sn + 16 * w + (lane & 15)];
+        re[w] = MF::mma(a.x, b.x, re[w]);
+        im[w] = MF::mma(a.x, b.y, im[w]);
+        re[w] = MF::mma(-a.y, b.y, re[w]);
+        im[w] = MF::mma(a.y, b.x, im[w]);
+      }
     }
     __syncthreads();
   }
-  const int n = col0 + sn + (lane & 15);
-  for (int i = 0; i < 4; ++i) {
-    const int m = row0 + sm + MF::row(lane, i);
-    if (m < M && n < N) C[(size_t)m * ldc + n] = cvt<TC>(mk<ACC>(re[i], im[i]));
+#pragma unroll
+  for (int w = 0; w < WB; ++w) {
+    const int n = col0 + sn + 16 * w + (lane & 15);
+    for (int i = 0; i < 4; ++i) {
+      const int m = row0 + sm + MF::row(lane, i);
+      if (m < M && n < N) C[(size_t)m * ldc + n] = cvt<TC>(mk<ACC>(re[w][i], im[w][i]));
+    }
   }
 }
 
@@ -496,6 +574,25 @@ __device__ void bargmax(double v, int i, double &vo, int &io, double *rv, int *r
     if (rv[w] > vo || (rv[w] == vo && ri[w] < io)) { vo = rv[w]; io = ri[w]; }
 }
 
+// Sum over aligned groups of 8 lanes, each lane receiving its group's sum,
+// on the DPP lane network (two quad permutations, then the mirror of the
+// half row) instead of LDS-routed shuffles.  All 8 lanes of a group must be
+// active.  Each lane ends with (x_i + x_(i^1)) + (x_(i^2) + x_(i^3)) plus
+// the same for the other quad, the sums a butterfly of xor-shuffles forms.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  return v;
+}
+
 // Eigen-decomposition of a Hermitian positive semi-definite matrix G
 // (nn x nn, leading dimension ld, in LDS or global memory; overwritten):
 // the reduced density of a truncation step, whose numerical rank is often
@@ -526,7 +623,8 @@ __device__ void bargmax(double v, int i, double &vo, int &io, double *rv, int *r
 //     (e_0 when r = 0).
 // Scratch: piv, pos (nn ints), dg (nn doubles).  Returns (to every thread)
 // the flops executed; *sweeps_out (thread 0) <- Jacobi sweeps.
-constexpr int kEigTpp = 8;        // threads per row pair
+constexpr int kEigTpp = 8;        // threads per row pair (the width of sum8)
+constexpr int kEigRegN = 32;      // rows up to this length are held in registers per round
 constexpr int kEigMaxSweeps = 40;
 
 template <int NT>
@@ -619,31 +717,59 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
           c64 *X = G + (size_t)piv[p] * ld, *Y = G + (size_t)piv[q] * ld;
           double a = 0, b = 0;
           c64 cc = mk<double>(0, 0);
-          for (int j = li; j < nn; j += TPP) {
-            const c64 xv = X[j], yv = Y[j];
-            a += norm2(xv);
-            b += norm2(yv);
-            cc = cc + xv * cj(yv);
-          }
+          // orders up to kEigRegN: the lane's elements of both rows stay in
+          // registers between the products and the rotation
+          c64 xr[kEigRegN / TPP], yr[kEigRegN / TPP];
+          if (nn <= kEigRegN) {
 #pragma unroll
-          for (int o = 1; o < TPP; o <<= 1) {
-            a += __shfl_xor(a, o, TPP);
-            b += __shfl_xor(b, o, TPP);
-            cc.x += __shfl_xor(cc.x, o, TPP);
-            cc.y += __shfl_xor(cc.y, o, TPP);
-          }
-          const double h = sqrt(norm2(cc)), ab = sqrt(a * b);
-          if (h > 0 && h > rot_tol * ab) {
-            const double d = b - a;
-            const double t = (d >= 0 ? 2.0 : -2.0) * h / (fabs(d) + sqrt(d * d + 4.0 * h * h));
-            const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs, ih = sn / h;
-            const c64 sg = mk<double>(cc.x * ih, cc.y * ih), sgc = cj(sg);
+            for (int u = 0; u < kEigRegN / TPP; ++u) {
+              const int j = li + u * TPP;
+              xr[u] = j < nn ? X[j] : mk<double>(0, 0);
+              yr[u] = j < nn ? Y[j] : mk<double>(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kEigRegN / TPP; ++u) {
+              a += norm2(xr[u]);
+              b += norm2(yr[u]);
+              cc = cc + xr[u] * cj(yr[u]);
+            }
+          } else {
             for (int j = li; j < nn; j += TPP) {
               const c64 xv = X[j], yv = Y[j];
-              X[j] = cs * xv - sg * yv;
-              Y[j] = sgc * xv + cs * yv;
+              a += norm2(xv);
+              b += norm2(yv);
+              cc = cc + xv * cj(yv);
             }
-            if (h > conv_tol * ab) rot = 1;
+          }
+          a = sum8(a);
+          b = sum8(b);
+          cc.x = sum8(cc.x);
+          cc.y = sum8(cc.y);
+          // in terms of h2 = |c|^2: t = tau |c|, cs = 1 / sqrt(1 + t^2),
+          // sg = sn c / |c| = tau cs c
+          const double h2 = norm2(cc), ab = a * b;
+          if (h2 > 0 && h2 > rot_tol * rot_tol * ab) {
+            const double d = b - a;
+            const double tau = (d >= 0 ? 2.0 : -2.0) / (fabs(d) + sqrt(d * d + 4.0 * h2));
+            const double cs = rsqrt(1.0 + tau * tau * h2), ts = tau * cs;
+            const c64 sg = mk<double>(cc.x * ts, cc.y * ts), sgc = cj(sg);
+            if (nn <= kEigRegN) {
+#pragma unroll
+              for (int u = 0; u < kEigRegN / TPP; ++u) {
+                const int j = li + u * TPP;
+                if (j < nn) {
+                  X[j] = cs * xr[u] - sg * yr[u];
+                  Y[j] = sgc * xr[u] + cs * yr[u];
+                }
+              }
+            } else {
+              for (int j = li; j < nn; j += TPP) {
+                const c64 xv = X[j], yv = Y[j];
+                X[j] = cs * xv - sg * yv;
+                Y[j] = sgc * xv + cs * yv;
+              }
+            }
+            if (h2 > conv_tol * conv_tol * ab) rot = 1;
           }
         }
         __syncthreads();
@@ -665,8 +791,7 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
         const c64 *X = G + (size_t)piv[i] * ld;
         for (int j = li; j < nn; j += TPP) a += norm2(X[j]);
       }
-#pragma unroll
-      for (int o = 1; o < TPP; o <<= 1) a += __shfl_xor(a, o, TPP);
+      a = sum8(a);
       if (i < r && li == 0) dg[i] = a;
     }
   }
@@ -683,12 +808,13 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
   }
   for (int i = r + tid; i < nn; i += NT) ev[i] = 0;
   __syncthreads();
-  for (int e = tid; e < r * nn; e += NT) {
-    const int c = e / nn, i = e - c * nn;
-    const double nr = dg[c];
-    const double inv = nr > 0 ? 1.0 / sqrt(nr) : 0.0;
-    Vout[(size_t)i * nn + pos[c]] = inv * cj(G[(size_t)piv[c] * ld + i]);
-  }
+  blk_each_rc<NT, 4, c64>(
+      r, nn, [&](int c, int i) { return G[(size_t)piv[c] * ld + i]; },
+      [&](int c, int i, c64 v) {
+        const double nr = dg[c];
+        const double inv = nr > 0 ? 1.0 / sqrt(nr) : 0.0;
+        Vout[(size_t)i * nn + pos[c]] = inv * cj(v);
+      });
   if (r == 0)
     for (int i = tid; i < nn; i += NT) Vout[(size_t)i * nn] = mk<double>(i == 0 ? 1.0 : 0.0, 0);
   if (sweeps_out && tid == 0) *sweeps_out = sweeps;
@@ -746,12 +872,12 @@ __device__ int select_body(const MpsDev &m, int s, int j, const c64 *V, cplx<T> 
   __syncthreads();
   const int k = kk;
   cplx<T> *site = slot<T>(m, j, s);
-  for (int e = threadIdx.x; e < nn * k; e += NT) {
-    int i = e / k, c = e % k;
-    cplx<T> v = cvt<T>(V[(size_t)i * nn + c]);
-    Vt[e] = v;
-    site[(size_t)c * nn + i] = cj(v);
-  }
+  blk_each_rc<NT, 4, cplx<T>>(
+      nn, k, [&](int i, int c) { return cvt<T>(V[(size_t)i * nn + c]); },
+      [&](int i, int c, cplx<T> v) {
+        Vt[(size_t)i * k + c] = v;
+        site[(size_t)c * nn + i] = cj(v);
+      });
   if (threadIdx.x == 0) {
     bnd(m, s)[j] = k;
     bnd(m, s)[j + 1] = w[j + 1];
@@ -767,7 +893,7 @@ __device__ void finish_body(const MpsDev &m, int s, int l, const cplx<T> *X) {
   int *w = wbd(m, s);
   const int cnt = w[l] * 2 * w[l + 1];
   double part = 0;
-  for (int e = threadIdx.x; e < cnt; e += NT) part += norm2(cvt<double>(X[e]));
+  blk_each<NT, 4, double>(cnt, [&](int e) { return norm2(cvt<double>(X[e])); }, [&](int, double v) { part += v; });
   const double n2 = bsum<NT>(part);
   if (m.keep_norm ? (isinf(n2) || !(n2 == n2)) : (!(n2 > 0) || isinf(n2))) {
     if (threadIdx.x == 0) atomicOr(m.err, STN_ERR_NUMERIC);
@@ -776,7 +902,8 @@ __device__ void finish_body(const MpsDev &m, int s, int l, const cplx<T> *X) {
   }
   const double inv = m.keep_norm ? 1.0 : 1.0 / sqrt(n2);
   cplx<T> *out = slot<T>(m, l, s);
-  for (int e = threadIdx.x; e < cnt; e += NT) out[e] = cvt<T>(inv * cvt<double>(X[e]));
+  blk_each<NT, 4, cplx<T>>(cnt, [&](int e) { return X[e]; },
+                           [&](int e, cplx<T> v) { out[e] = cvt<T>(inv * cvt<double>(v)); });
   if (threadIdx.x == 0) {
     bnd(m, s)[l + 1] = w[l + 1];
     m.nrm[s] = n2;
