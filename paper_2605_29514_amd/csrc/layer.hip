@@ -26,6 +26,7 @@ constexpr size_t kLdsQrMat = 16 * 1024;   // QR operand in LDS up to this many b
 constexpr int kEigIdx = 64;               // eigen-solve index / pair tables in LDS up to this order
 constexpr int kJacLdsN = 32;              // FP64 path: Jacobi G and V in LDS up to this order
 constexpr int kEigLdsMax = 64;            // FP32 path: factor in LDS up to this order
+constexpr int kDirectGemm = 64;           // products with every dimension up to this skip LDS staging
 
 // Dynamic LDS layout (bytes): small arrays at fixed offsets, then one
 // region that the phases overlay (GEMM staging, QR operand, the eigen-solve
@@ -44,13 +45,39 @@ constexpr size_t kPiv = kPs + kPh * sizeof(double);             // int[kEigIdx]
 constexpr size_t kPos = kPiv + kEigIdx * sizeof(int);           // int[kEigIdx + 2]
 constexpr size_t kPp = kPos + (kEigIdx + 2) * sizeof(int);      // int[kPh]
 constexpr size_t kPq = kPp + kPh * sizeof(int);                 // int[kPh]
-constexpr size_t kWp = (kPq + kPh * sizeof(int) + 15) / 16 * 16;  // c64[NT]
+constexpr size_t kEv = (kPq + kPh * sizeof(int) + 7) / 8 * 8;  // double[kEigIdx]
+constexpr size_t kWp = (kEv + kEigIdx * sizeof(double) + 15) / 16 * 16;  // c64[NT]
 constexpr size_t kUfix = cmax(kLdsQrMat, GemmStage<double>::bytes);
 constexpr size_t u_off(int nt) { return (kWp + nt * sizeof(c64) + 255) / 256 * 256; }
 constexpr size_t eig_region(bool fp64, int en) {
   return fp64 ? 2 * (size_t)kJacLdsN * (kJacLdsN + 1) * sizeof(c64) : (size_t)en * (en + 1) * sizeof(c64);
 }
-constexpr size_t lds_bytes(int nt, bool fp64, int en) { return u_off(nt) + cmax(kUfix, eig_region(fp64, en)); }
+// FP32 path, steps small enough for the direct GEMMs (every dimension up to
+// kDirectGemm, so no GEMM staging runs while these hold live data): three
+// buffers after the fixed arrays.
+//   [u_off, +kStepFactor): the factor of a truncation step of order up to
+//     kLdsStepN; after the selection, N = X V^T
+//   [vt_off, +kVtBytes): V^T (nn x k), or before it the F = E X of the
+//     step's Gram when that fits
+//   [x_off, +kXBytes): the centre block X of the right-to-left sweep, kept
+//     from step to step
+// The environment sweep, before X exists, uses the last two as one buffer
+// for its F = E B (kFElems FP64).  The GEMM staging overlaps only the first
+// bytes of V^T.  At 128 threads per shot four blocks still fit a compute
+// unit's 160 KB.
+constexpr int kLdsStepN = 32;
+constexpr size_t kStepFactor = (size_t)kLdsStepN * (kLdsStepN + 1) * sizeof(c64);
+constexpr size_t kVtBytes = (size_t)kLdsStepN * kLdsStepN * sizeof(cplx<float>);
+constexpr size_t kXBytes = 8192;
+constexpr int kXElems = kXBytes / sizeof(cplx<float>);
+constexpr int kFElems = (kVtBytes + kXBytes) / sizeof(c64);
+constexpr size_t vt_off(int nt) { return u_off(nt) + kStepFactor; }
+constexpr size_t x_off(int nt) { return vt_off(nt) + kVtBytes; }
+static_assert(x_off(64) - u_off(64) >= kUfix, "GEMM staging reaches the X buffer");
+constexpr size_t lds_bytes(int nt, bool fp64, int en) {
+  return u_off(nt) + cmax(cmax(kUfix, eig_region(fp64, en)), fp64 ? 0 : kStepFactor + kVtBytes + kXBytes);
+}
+static_assert(lds_bytes(128, false, 32) * 4 <= 160 * 1024, "four 128-thread blocks per compute unit");
 // FP32 path: factors up to order 64 in LDS when chi_max is 17..32 (every
 // doubled bond then fits, at ~70 KB per block); otherwise up to 32 (~22 KB)
 // and larger orders in the shot's global scratch.
@@ -81,7 +108,10 @@ __device__ inline Fallback fallback(const MpsDev &m, int s) {
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void blk_gemm(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
                          const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, char *lds) {
-  gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds + u_off(NT));
+  if (M <= kDirectGemm && N <= kDirectGemm && K <= kDirectGemm)
+    gemm_direct<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc);
+  else
+    gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds + u_off(NT));
   __syncthreads();
 }
 
@@ -301,6 +331,13 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
   clk.lap(m, 2);
   c64 *Es = m.Es + (size_t)s * m.Es_cap, *Fs = m.Fs + (size_t)s * m.Fs_cap;
   const int eb2 = m.ebond * m.ebond;
+  // the centre block X of the right-to-left sweep: the shot's T, or (FP32
+  // path, a step small enough for the LDS buffers) the LDS X buffer
+  cplx<T> *Xg = scr<T>(m.T, m.T_cap, s), *Xl = reinterpret_cast<cplx<T> *>(lds + x_off(NT));
+  auto x_fits = [&](int lx, int n2) {
+    return sizeof(T) == 4 && n2 <= kLdsStepN && lx <= kDirectGemm && lx * n2 <= kXElems;
+  };
+  bool xl = false;
   if (env) {
     // E_l = B_l^H B_l (B_l as 2 w[l] x w[l+1]); then E_j through site r-1
     {
@@ -314,15 +351,26 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     for (int j = l + 1; j < r; ++j) {
       const int Dl = w[j], Dr = w[j + 1];
       c64 *Ep = Es + (size_t)(j - 1 - l) * eb2, *Ej = Es + (size_t)(j - l) * eb2;
-      blk_gemm<double, T, double, double, NT>(Dl, 2 * Dr, Dl, Ep, Dl, 0, wslot<T>(m, j, s), 2 * Dr, 0, Fs, 2 * Dr, lds);
-      blk_gemm<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, Fs, Dr, 0, Ej, Dr, lds);
+      // FP32 path, small sites: F in LDS between two direct GEMMs
+      const bool lf = sizeof(T) == 4 && Dl <= kDirectGemm / 2 && Dr <= kDirectGemm / 2 && Dl * 2 * Dr <= kFElems;
+      c64 *F = lf ? reinterpret_cast<c64 *>(lds + vt_off(NT)) : Fs;
+      if (lf) {
+        gemm_direct<double, T, double, double, NT>(Dl, 2 * Dr, Dl, Ep, Dl, 0, wslot<T>(m, j, s), 2 * Dr, 0, F, 2 * Dr);
+        __syncthreads();
+        gemm_direct<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, F, Dr, 0, Ej, Dr);
+        __syncthreads();
+      } else {
+        blk_gemm<double, T, double, double, NT>(Dl, 2 * Dr, Dl, Ep, Dl, 0, wslot<T>(m, j, s), 2 * Dr, 0, F, 2 * Dr, lds);
+        blk_gemm<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, F, Dr, 0, Ej, Dr, lds);
+      }
       if (tid == 0) {
         const double f = gemm_flops(Dl, 2 * Dr, Dl) + gemm_flops(Dr, Dr, 2 * Dl);
         add_work(m, cls, f, (double)sizeof(cplx<T>) * 2 * Dl * Dr + 16.0 * (Dl * Dl + 2.0 * Dl * Dr + Dr * Dr));
         if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], f);
       }
     }
-    blk_copy<T, NT>(scr<T>(m.T, m.T_cap, s), wslot<T>(m, r, s), 2 * w[r] * w[r + 1]);
+    xl = x_fits(w[r], 2 * w[r + 1]);
+    blk_copy<T, NT>(xl ? Xl : Xg, wslot<T>(m, r, s), 2 * w[r] * w[r + 1]);
     clk.lap(m, 3);
   }
   // left-to-right QR sweep: B_j = Q R, Q -> workspace slot j, R B_{j+1} -> T
@@ -344,21 +392,35 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
   // right-to-left truncation sweep
   for (int j = r; j > l; --j) {
     const int Lx = w[j], nn = 2 * w[j + 1];
-    cplx<T> *X = scr<T>(m.T, m.T_cap, s);
+    cplx<T> *X = xl ? Xl : Xg;
     c64 *Gg = m.G + s * m.G_cap;
+    // FP32 path, small steps: rho goes straight into the LDS factor, and the
+    // eigenvectors and V^T stay in LDS (each global write read back after a
+    // barrier costs a store and a load latency on the step's critical path)
+    const bool ls = sizeof(T) == 4 && nn <= kLdsStepN && Lx <= kDirectGemm;
+    c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
     if (env) {                                // rho = X^H (E_{j-1} X)
       const c64 *Ep = Es + (size_t)(j - 1 - l) * eb2;
-      blk_gemm<double, T, double, double, NT>(Lx, nn, Lx, Ep, Lx, 0, X, nn, 0, Fs, nn, lds);
-      blk_gemm<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, Fs, nn, 0, Gg, nn, lds);
+      c64 *F = ls && Lx * nn * sizeof(c64) <= kVtBytes ? reinterpret_cast<c64 *>(lds + vt_off(NT)) : Fs;
+      blk_gemm<double, T, double, double, NT>(Lx, nn, Lx, Ep, Lx, 0, X, nn, 0, F, nn, lds);
+      if (ls) {
+        gemm_direct<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, F, nn, 0, Gl, nn + 1);
+        __syncthreads();
+      } else {
+        blk_gemm<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, Fs, nn, 0, Gg, nn, lds);
+      }
       if (tid == 0) {
         add_work(m, cls, gemm_flops(Lx, nn, Lx), 16.0 * (Lx * Lx + Lx * nn));
         if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(Lx, nn, Lx));
       }
+    } else if (ls) {
+      gemm_direct<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gl, nn + 1);
+      __syncthreads();
     } else {
       blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
     }
     clk.lap(m, 5);
-    const c64 *Vsel;                          // sorted eigenvectors, nn x nn
+    const c64 *Vsel = m.V + s * m.V_cap;     // sorted eigenvectors, nn x nn (not in LDS steps)
     {
       const Fallback f = fallback(m, s);
       const bool li = nn <= kEigIdx;
@@ -375,7 +437,6 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         c64 *Gw = Gg, *Vw = m.V + s * m.V_cap;
         int ldw = nn;
         if (nn <= kJacLdsN) {
-          c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
           ldw = nn + 1;
           blk_each_rc<NT, 8, c64>(nn, nn, [&](int i, int j) { return Gg[i * nn + j]; },
                                   [&](int i, int j, c64 v) { Gl[i * ldw + j] = v; });
@@ -392,23 +453,26 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         const double ct = chol_tol(m.eps_cut, nn);
         double *ev = m.ev + s * m.ev_cap;
         c64 *V = m.V + s * m.V_cap;
-        if (nn <= eig_n) {
+        int *piv_l = reinterpret_cast<int *>(lds + kPiv), *pos_l = reinterpret_cast<int *>(lds + kPos);
+        double *dg_l = reinterpret_cast<double *>(lds + kDg);
+        if (ls) {
+          // eigenvalues to LDS, eigenvectors left in the factor rows
+          fe = eig_psd<NT>(nn, Gl, nn + 1, reinterpret_cast<double *>(lds + kEv), nullptr, m.err, piv_l, pos_l,
+                           dg_l, sweeps, ct, eig_conv_tol<T>(), eig_rot_tol<T>());
+        } else if (nn <= eig_n) {
           // factor (rows padded by one) and index tables all in LDS: a call
           // of its own, so that every access in it is a direct LDS access
-          c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
           const int ldw = nn + 1;
           blk_each_rc<NT, 8, c64>(nn, nn, [&](int i, int j) { return Gg[i * nn + j]; },
                                   [&](int i, int j, c64 v) { Gl[i * ldw + j] = v; });
           __syncthreads();
-          fe = eig_psd<NT>(nn, Gl, ldw, ev, V, m.err, reinterpret_cast<int *>(lds + kPiv),
-                           reinterpret_cast<int *>(lds + kPos), reinterpret_cast<double *>(lds + kDg), sweeps, ct,
-                           eig_conv_tol<T>(), eig_rot_tol<T>());
+          fe = eig_psd<NT>(nn, Gl, ldw, ev, V, m.err, piv_l, pos_l, dg_l, sweeps, ct, eig_conv_tol<T>(),
+                           eig_rot_tol<T>());
         } else {
-          int *piv = li ? reinterpret_cast<int *>(lds + kPiv) : f.piv;
-          double *dg = li ? reinterpret_cast<double *>(lds + kDg) : f.dg;
+          int *piv = li ? piv_l : f.piv;
+          double *dg = li ? dg_l : f.dg;
           fe = eig_psd<NT>(nn, Gg, nn, ev, V, m.err, piv, pos, dg, sweeps, ct, eig_conv_tol<T>(), eig_rot_tol<T>());
         }
-        Vsel = m.V + s * m.V_cap;
       }
       if (tid == 0) {
         const double f64 = gemm_flops(nn, nn, Lx) + fe;
@@ -418,11 +482,32 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
       }
       clk.lap(m, 6);
     }
-    cplx<T> *Vt = scr<T>(m.Vt, m.Vt_cap, s);
-    const int k = select_body<T, NT>(m, s, j, Vsel, Vt);
-    cplx<T> *Nn = scr<T>(m.N, m.N_cap, s);
-    blk_gemm<T, T, T, T, NT>(Lx, k, nn, X, nn, 0, Vt, k, 0, Nn, k, lds);
+    int k;
+    cplx<T> *Vt = ls ? reinterpret_cast<cplx<T> *>(lds + vt_off(NT)) : scr<T>(m.Vt, m.Vt_cap, s);
+    if (ls) {
+      const double *evl = reinterpret_cast<const double *>(lds + kEv);
+      const int *rk = reinterpret_cast<const int *>(lds + kPos), *pv = reinterpret_cast<const int *>(lds + kPiv);
+      const double *rn = reinterpret_cast<const double *>(lds + kDg);
+      const int ldw = nn + 1;
+      k = select_core<T, NT>(
+          m, s, j, evl,
+          [&](int i, int c) {
+            if (evl[0] == 0) return mk<double>(i == 0 && c == 0 ? 1.0 : 0.0, 0);   // rank 0: e_0
+            const int row = rk[c];
+            return rn[row] * cj(Gl[(size_t)pv[row] * ldw + i]);
+          },
+          Vt);
+    } else {
+      k = select_body<T, NT>(m, s, j, Vsel, Vt);
+    }
     const int M = 2 * w[j - 1];
+    // N in the factor buffer (dead after the selection) when the product
+    // that reads it is direct too; the new X in LDS when the next step
+    // qualifies (the old X is dead once N is formed)
+    cplx<T> *Nn = ls && M <= kDirectGemm ? reinterpret_cast<cplx<T> *>(lds + u_off(NT)) : scr<T>(m.N, m.N_cap, s);
+    blk_gemm<T, T, T, T, NT>(Lx, k, nn, X, nn, 0, Vt, k, 0, Nn, k, lds);
+    xl = x_fits(w[j - 1], 2 * k);
+    X = xl ? Xl : Xg;
     blk_gemm<T, T, T, T, NT>(M, k, Lx, wslot<T>(m, j - 1, s), Lx, 0, Nn, k, 0, X, k, lds);
     if (tid == 0) {
       w[j] = k;
@@ -431,7 +516,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     }
     __syncthreads();
   }
-  finish_body<T, NT>(m, s, l, scr<T>(m.T, m.T_cap, s));
+  finish_body<T, NT>(m, s, l, xl ? Xl : Xg);
   clk.lap(m, 7);
   c = l;
 }

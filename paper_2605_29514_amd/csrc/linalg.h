@@ -251,6 +251,74 @@ __device__ void gemm_tile(int M, int N, int K, const cplx<TA> *A, int lda, int o
   }
 }
 
+// C = op(A) op(B) (as gemm_tile) with operands read straight from memory
+// into the matrix-core lane layout, for products small enough that staging
+// through LDS (two barriers per k-step) costs more than it saves.  Each wave
+// owns pairs of 16x16 output blocks side by side along N and loads, per
+// 16 values of k, its lane's elements of A and of both B blocks together
+// before the multiplies: a product costs about one memory latency per
+// 16 k.  The k order of the accumulation is that of gemm_tile.
+template <typename TA, typename TB_, typename TC, typename ACC, int NT>
+__device__ void gemm_direct(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
+                            const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc) {
+  using MF = Mfma<ACC>;
+  using V = typename MF::V;
+  constexpr int NW = NT / 64, KC = 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int nbm = (M + 15) / 16, nbp = (N + 31) / 32;
+  for (int bp = wave; bp < nbm * nbp; bp += NW) {
+    const int m0 = (bp / nbp) * 16, n0 = (bp % nbp) * 32;
+    const int m = m0 + r16, n1 = n0 + r16, n2 = n0 + 16 + r16;
+    V re[2], im[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+      for (int i = 0; i < 4; ++i) { re[w][i] = 0; im[w][i] = 0; }
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      cplx<TA> a[KC / 4];
+      cplx<TB_> b1[KC / 4], b2[KC / 4];
+#pragma unroll
+      for (int kk = 0; kk < KC / 4; ++kk) {
+        const int k = k0 + 4 * kk + q;
+        a[kk] = mk<TA>(0, 0);
+        b1[kk] = mk<TB_>(0, 0);
+        b2[kk] = mk<TB_>(0, 0);
+        if (k < K) {
+          if (m < M) a[kk] = opA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
+          if (n1 < N) b1[kk] = opB ? B[(size_t)n1 * ldb + k] : B[(size_t)k * ldb + n1];
+          if (n2 < N) b2[kk] = opB ? B[(size_t)n2 * ldb + k] : B[(size_t)k * ldb + n2];
+        }
+      }
+      const int kend = K - k0 < KC ? K - k0 : KC;
+#pragma unroll
+      for (int kk = 0; kk < KC / 4; ++kk) {
+        if (4 * kk >= kend) break;
+        const cplx<ACC> av = opA ? cj(cvt<ACC>(a[kk])) : cvt<ACC>(a[kk]);
+        const cplx<ACC> bv1 = opB ? cj(cvt<ACC>(b1[kk])) : cvt<ACC>(b1[kk]);
+        const cplx<ACC> bv2 = opB ? cj(cvt<ACC>(b2[kk])) : cvt<ACC>(b2[kk]);
+        re[0] = MF::mma(av.x, bv1.x, re[0]);
+        im[0] = MF::mma(av.x, bv1.y, im[0]);
+        re[0] = MF::mma(-av.y, bv1.y, re[0]);
+        im[0] = MF::mma(av.y, bv1.x, im[0]);
+        if (n0 + 16 < N) {
+          re[1] = MF::mma(av.x, bv2.x, re[1]);
+          im[1] = MF::mma(av.x, bv2.y, im[1]);
+          re[1] = MF::mma(-av.y, bv2.y, re[1]);
+          im[1] = MF::mma(av.y, bv2.x, im[1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int n = n0 + 16 * w + r16;
+      for (int i = 0; i < 4; ++i) {
+        const int mm = m0 + MF::row(lane, i);
+        if (mm < M && n < N) C[(size_t)mm * ldc + n] = cvt<TC>(mk<ACC>(re[w][i], im[w][i]));
+      }
+    }
+  }
+}
+
 // All tiles of a product by the calling block (tiles t0, t0 + dt, ...).
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void gemm_tiles(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
@@ -551,29 +619,6 @@ template <typename T> __device__ inline double jac_abs() { return 1e-18; }
 template <typename T> __device__ inline double jac_rel() { return 1e-15; }
 
 // ------------------------------------------------ eigen-solve (FP64)
-// Block-wide argmax of (v, i): largest v, ties to the smaller i; every
-// thread receives the result.  The partials go to buffer `buf` (0 or 1) of
-// the caller's rv / ri (2 x NT/64 entries each): calls that alternate the
-// buffer need only the one barrier inside, as long as some barrier
-// separates every call from the one two calls earlier.
-template <int NT>
-__device__ void bargmax(double v, int i, double &vo, int &io, double *rv, int *ri, int buf) {
-  constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
-  for (int o = 32; o > 0; o >>= 1) {
-    const double v2 = __shfl_xor(v, o, 64);
-    const int i2 = __shfl_xor(i, o, 64);
-    if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
-  }
-  rv += buf * NW;
-  ri += buf * NW;
-  if ((threadIdx.x & 63) == 0) { rv[threadIdx.x >> 6] = v; ri[threadIdx.x >> 6] = i; }
-  __syncthreads();
-  vo = rv[0];
-  io = ri[0];
-  for (int w = 1; w < NW; ++w)
-    if (rv[w] > vo || (rv[w] == vo && ri[w] < io)) { vo = rv[w]; io = ri[w]; }
-}
-
 // Sum over aligned groups of 8 lanes, each lane receiving its group's sum,
 // on the DPP lane network (two quad permutations, then the mirror of the
 // half row) instead of LDS-routed shuffles.  All 8 lanes of a group must be
@@ -586,11 +631,76 @@ __device__ __forceinline__ double dpp_mov(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+__device__ __forceinline__ double readlane(double v, int lane) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 __device__ __forceinline__ double sum8(double v) {
   v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
   v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
   v += dpp_mov<0x141>(v);   // row_half_mirror
   return v;
+}
+
+// The same over aligned groups of g = 8 or 16 lanes (one more step, the
+// mirror of the row of 16, for g = 16).
+__device__ __forceinline__ double sumg(double v, int g) {
+  v = sum8(v);
+  if (g == 16) v += dpp_mov<0x140>(v);    // row_mirror
+  return v;
+}
+
+// Block-wide argmax of (v, i): largest v, ties to the smaller i; every
+// thread receives the result.  Within a wave: DPP steps inside each row of
+// 16 lanes (the choice is symmetric, so exchanging with any lane of the
+// other half gives every lane the half's winner), then the four row winners
+// read as scalars.  Waves: the partials go to buffer `buf` (0 or 1) of the
+// caller's rv / ri (2 x NT/64 entries each): calls that alternate the
+// buffer need only the one barrier inside, as long as some barrier
+// separates every call from the one two calls earlier.  Every lane of the
+// block must take part.
+template <int NT>
+__device__ void bargmax(double v, int i, double &vo, int &io, double *rv, int *ri, int buf) {
+  constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
+  auto take = [&](double v2, int i2) {
+    if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+  };
+  take(dpp_mov<0xB1>(v), dpp_mov<0xB1>(i));     // quad_perm [1, 0, 3, 2]
+  take(dpp_mov<0x4E>(v), dpp_mov<0x4E>(i));     // quad_perm [2, 3, 0, 1]
+  take(dpp_mov<0x141>(v), dpp_mov<0x141>(i));   // row_half_mirror
+  take(dpp_mov<0x140>(v), dpp_mov<0x140>(i));   // row_mirror
+  {
+    double bv = readlane(v, 0);
+    int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+      const double v2 = readlane(v, 16 * r);
+      const int i2 = __builtin_amdgcn_readlane(i, 16 * r);
+      if (v2 > bv || (v2 == bv && i2 < bi)) { bv = v2; bi = i2; }
+    }
+    v = bv;
+    i = bi;
+  }
+  if constexpr (NW == 1) {
+    __syncthreads();                            // the caller's barrier per call
+    vo = v;
+    io = i;
+  } else {
+    rv += buf * NW;
+    ri += buf * NW;
+    if ((threadIdx.x & 63) == 0) { rv[threadIdx.x >> 6] = v; ri[threadIdx.x >> 6] = i; }
+    __syncthreads();
+    vo = rv[0];
+    io = ri[0];
+    for (int w = 1; w < NW; ++w)
+      if (rv[w] > vo || (rv[w] == vo && ri[w] < io)) { vo = rv[w]; io = ri[w]; }
+  }
 }
 
 // Eigen-decomposition of a Hermitian positive semi-definite matrix G
@@ -620,7 +730,9 @@ __device__ __forceinline__ double sum8(double v) {
 //     c^H: eigenvalue |u_c|^2, eigenvector u_c / |u_c|.  ev <- eigenvalues
 //     in descending order (0 past r); column j of Vout (nn x nn, leading
 //     dimension nn, distinct from G) <- the eigenvector of ev[j] for j < r
-//     (e_0 when r = 0).
+//     (e_0 when r = 0).  With Vout null the eigenvectors stay where they
+//     are: for j < r, eigenvector j = conj(row piv[pos[j]] of G) times
+//     dg[pos[j]] (pos then maps rank to factor row, dg holds 1 / |u_c|).
 // Scratch: piv, pos (nn ints), dg (nn doubles).  Returns (to every thread)
 // the flops executed; *sweeps_out (thread 0) <- Jacobi sweeps.
 constexpr int kEigTpp = 8;        // threads per row pair (the width of sum8)
@@ -700,9 +812,11 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
   // 2. one-sided Jacobi on the rows piv[0..r)
   int sweeps = 0;
   if (r >= 2) {
-    constexpr int TPP = kEigTpp, GP = NT / kEigTpp;
+    // 16 lanes per pair when every pair of a round then still has its own
+    // lanes (half the work per lane), else kEigTpp
     const int P = r + (r & 1), H = P / 2;
-    const int li = tid % TPP, gi = tid / TPP;
+    const int TPP = H <= NT / 16 ? 16 : kEigTpp, GP = NT / TPP;
+    const int li = tid & (TPP - 1), gi = tid / TPP;
     for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
       int rot = 0;
       for (int rnd = 0; rnd < P - 1; ++rnd) {
@@ -719,16 +833,16 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
           c64 cc = mk<double>(0, 0);
           // orders up to kEigRegN: the lane's elements of both rows stay in
           // registers between the products and the rotation
-          c64 xr[kEigRegN / TPP], yr[kEigRegN / TPP];
+          c64 xr[kEigRegN / kEigTpp], yr[kEigRegN / kEigTpp];
           if (nn <= kEigRegN) {
 #pragma unroll
-            for (int u = 0; u < kEigRegN / TPP; ++u) {
+            for (int u = 0; u < kEigRegN / kEigTpp; ++u) {
               const int j = li + u * TPP;
               xr[u] = j < nn ? X[j] : mk<double>(0, 0);
               yr[u] = j < nn ? Y[j] : mk<double>(0, 0);
             }
 #pragma unroll
-            for (int u = 0; u < kEigRegN / TPP; ++u) {
+            for (int u = 0; u < kEigRegN / kEigTpp; ++u) {
               a += norm2(xr[u]);
               b += norm2(yr[u]);
               cc = cc + xr[u] * cj(yr[u]);
@@ -741,10 +855,10 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
               cc = cc + xv * cj(yv);
             }
           }
-          a = sum8(a);
-          b = sum8(b);
-          cc.x = sum8(cc.x);
-          cc.y = sum8(cc.y);
+          a = sumg(a, TPP);
+          b = sumg(b, TPP);
+          cc.x = sumg(cc.x, TPP);
+          cc.y = sumg(cc.y, TPP);
           // in terms of h2 = |c|^2: t = tau |c|, cs = 1 / sqrt(1 + t^2),
           // sg = sn c / |c| = tau cs c
           const double h2 = norm2(cc), ab = a * b;
@@ -755,7 +869,7 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
             const c64 sg = mk<double>(cc.x * ts, cc.y * ts), sgc = cj(sg);
             if (nn <= kEigRegN) {
 #pragma unroll
-              for (int u = 0; u < kEigRegN / TPP; ++u) {
+              for (int u = 0; u < kEigRegN / kEigTpp; ++u) {
                 const int j = li + u * TPP;
                 if (j < nn) {
                   X[j] = cs * xr[u] - sg * yr[u];
@@ -804,19 +918,24 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
       rank += (lj > l) || (lj == l && j < i);
     }
     ev[rank] = l;
-    pos[i] = rank;
+    if (Vout) pos[i] = rank;
+    else pos[rank] = i;
   }
   for (int i = r + tid; i < nn; i += NT) ev[i] = 0;
   __syncthreads();
-  blk_each_rc<NT, 4, c64>(
-      r, nn, [&](int c, int i) { return G[(size_t)piv[c] * ld + i]; },
-      [&](int c, int i, c64 v) {
-        const double nr = dg[c];
-        const double inv = nr > 0 ? 1.0 / sqrt(nr) : 0.0;
-        Vout[(size_t)i * nn + pos[c]] = inv * cj(v);
-      });
-  if (r == 0)
-    for (int i = tid; i < nn; i += NT) Vout[(size_t)i * nn] = mk<double>(i == 0 ? 1.0 : 0.0, 0);
+  if (Vout) {
+    blk_each_rc<NT, 4, c64>(
+        r, nn, [&](int c, int i) { return G[(size_t)piv[c] * ld + i]; },
+        [&](int c, int i, c64 v) {
+          const double nr = dg[c];
+          const double inv = nr > 0 ? 1.0 / sqrt(nr) : 0.0;
+          Vout[(size_t)i * nn + pos[c]] = inv * cj(v);
+        });
+    if (r == 0)
+      for (int i = tid; i < nn; i += NT) Vout[(size_t)i * nn] = mk<double>(i == 0 ? 1.0 : 0.0, 0);
+  } else {
+    for (int c = tid; c < r; c += NT) dg[c] = dg[c] > 0 ? 1.0 / sqrt(dg[c]) : 0.0;
+  }
   if (sweeps_out && tid == 0) *sweeps_out = sweeps;
   __syncthreads();
   return flops;
@@ -838,12 +957,12 @@ __device__ inline double chol_tol(double eps_cut, int nn) { return fmax(eps_cut 
 // Keep k' = min(chi_max, #{lambda_i > eps sum lambda}, 2^min(j, n-j)) largest
 // (at least 1); the discarded weight updates the fidelity; Vt = V[:, :k']
 // (nn x k'); site j <- Vt^H as (k', 2, wb[j+1]); bond[j] = k',
-// bond[j+1] = wb[j+1].  The sorted eigenvectors (ld nn) are read from V.
-template <typename T, int NT>
-__device__ int select_body(const MpsDev &m, int s, int j, const c64 *V, cplx<T> *Vt) {
+// bond[j+1] = wb[j+1].  ev: the sorted eigenvalues (nn); vload(i, c):
+// element i of the eigenvector of ev[c].
+template <typename T, int NT, typename VF>
+__device__ int select_core(const MpsDev &m, int s, int j, const double *ev, VF vload, cplx<T> *Vt) {
   int *w = wbd(m, s);
   const int nn = 2 * w[j + 1];
-  const double *ev = m.ev + s * m.ev_cap;
   __shared__ int kk;
   double part = 0;
   for (int i = threadIdx.x; i < nn; i += NT) part += fmax(ev[i], 0.0);
@@ -873,7 +992,7 @@ __device__ int select_body(const MpsDev &m, int s, int j, const c64 *V, cplx<T> 
   const int k = kk;
   cplx<T> *site = slot<T>(m, j, s);
   blk_each_rc<NT, 4, cplx<T>>(
-      nn, k, [&](int i, int c) { return cvt<T>(V[(size_t)i * nn + c]); },
+      nn, k, [&](int i, int c) { return cvt<T>(vload(i, c)); },
       [&](int i, int c, cplx<T> v) {
         Vt[(size_t)i * k + c] = v;
         site[(size_t)c * nn + i] = cj(v);
@@ -884,6 +1003,12 @@ __device__ int select_body(const MpsDev &m, int s, int j, const c64 *V, cplx<T> 
   }
   __syncthreads();
   return k;
+}
+// The sorted eigenvalues in m.ev, the eigenvectors in V (ld nn).
+template <typename T, int NT>
+__device__ int select_body(const MpsDev &m, int s, int j, const c64 *V, cplx<T> *Vt) {
+  const int nn = 2 * wbd(m, s)[j + 1];
+  return select_core<T, NT>(m, s, j, m.ev + s * m.ev_cap, [&](int i, int c) { return V[(size_t)i * nn + c]; }, Vt);
 }
 
 // Centre at l: normalise X (wb[l], 2, wb[l+1]) in FP64 into slot l;
