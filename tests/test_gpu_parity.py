@@ -146,6 +146,16 @@ def test_random_gate_set_tableau(B):
     run_parity(B, circ, 64, "fp64", range(5))
 
 
+def test_fp32_fused_both_step_routes(B):
+    """FP32, fused kernel at 128 threads per shot (the bench's schedule), on a
+    circuit whose bonds reach 32: truncation steps of order above 32 take the
+    global-scratch route, the smaller ones hand over through LDS, in one run."""
+    from _circuits import entangling_circuit
+    circ = entangling_circuit(14, 20, 6, 7, meas_every=6)
+    _, ores, _ = run_parity(B, circ, 64, "fp32", range(0, 6, 2), mode=(2, 128))
+    assert max(o.max_bond for o in ores.values()) > 16
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_d3_crosstalk_no_truncation(B, prec, mode):
