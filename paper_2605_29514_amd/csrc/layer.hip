@@ -394,16 +394,19 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     const int Lx = w[j], nn = 2 * w[j + 1];
     cplx<T> *X = xl ? Xl : Xg;
     c64 *Gg = m.G + s * m.G_cap;
-    // FP32 path, small steps: rho goes straight into the LDS factor, and the
-    // eigenvectors and V^T stay in LDS (each global write read back after a
-    // barrier costs a store and a load latency on the step's critical path)
-    const bool ls = sizeof(T) == 4 && nn <= kLdsStepN && Lx <= kDirectGemm;
+    // FP32 path: when the factor fits the LDS order in use and the products
+    // are direct, rho goes straight into the LDS factor and the selection
+    // reads the eigenvectors there (lg); small steps also keep V^T and their
+    // intermediates in LDS (ls).  Each global write read back after a barrier
+    // costs a store and a load latency on the step's critical path.
+    const bool lg = sizeof(T) == 4 && nn <= eig_n && nn <= kDirectGemm && Lx <= kDirectGemm;
+    const bool ls = lg && nn <= kLdsStepN;
     c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
     if (env) {                                // rho = X^H (E_{j-1} X)
       const c64 *Ep = Es + (size_t)(j - 1 - l) * eb2;
       c64 *F = ls && Lx * nn * sizeof(c64) <= kVtBytes ? reinterpret_cast<c64 *>(lds + vt_off(NT)) : Fs;
       blk_gemm<double, T, double, double, NT>(Lx, nn, Lx, Ep, Lx, 0, X, nn, 0, F, nn, lds);
-      if (ls) {
+      if (lg) {
         gemm_direct<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, F, nn, 0, Gl, nn + 1);
         __syncthreads();
       } else {
@@ -413,7 +416,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         add_work(m, cls, gemm_flops(Lx, nn, Lx), 16.0 * (Lx * Lx + Lx * nn));
         if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], gemm_flops(Lx, nn, Lx));
       }
-    } else if (ls) {
+    } else if (lg) {
       gemm_direct<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gl, nn + 1);
       __syncthreads();
     } else {
@@ -455,7 +458,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         c64 *V = m.V + s * m.V_cap;
         int *piv_l = reinterpret_cast<int *>(lds + kPiv), *pos_l = reinterpret_cast<int *>(lds + kPos);
         double *dg_l = reinterpret_cast<double *>(lds + kDg);
-        if (ls) {
+        if (lg) {
           // eigenvalues to LDS, eigenvectors left in the factor rows
           fe = eig_psd<NT>(nn, Gl, nn + 1, reinterpret_cast<double *>(lds + kEv), nullptr, m.err, piv_l, pos_l,
                            dg_l, sweeps, ct, eig_conv_tol<T>(), eig_rot_tol<T>());
@@ -484,7 +487,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     }
     int k;
     cplx<T> *Vt = ls ? reinterpret_cast<cplx<T> *>(lds + vt_off(NT)) : scr<T>(m.Vt, m.Vt_cap, s);
-    if (ls) {
+    if (lg) {
       const double *evl = reinterpret_cast<const double *>(lds + kEv);
       const int *rk = reinterpret_cast<const int *>(lds + kPos), *pv = reinterpret_cast<const int *>(lds + kPiv);
       const double *rn = reinterpret_cast<const double *>(lds + kDg);

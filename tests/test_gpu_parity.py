@@ -146,13 +146,16 @@ def test_random_gate_set_tableau(B):
     run_parity(B, circ, 64, "fp64", range(5))
 
 
-def test_fp32_fused_both_step_routes(B):
+@pytest.mark.parametrize("chi", [64, 32])
+def test_fp32_fused_both_step_routes(B, chi):
     """FP32, fused kernel at 128 threads per shot (the bench's schedule), on a
-    circuit whose bonds reach 32: truncation steps of order above 32 take the
-    global-scratch route, the smaller ones hand over through LDS, in one run."""
+    circuit whose bonds reach 32 (chi_max does not bind): the truncation steps
+    of order up to 32 hand over through LDS; the larger ones (orders 34..64)
+    keep rho and the eigenvectors in global scratch at chi_max 64 (LDS factor
+    order 32) and in the LDS factor at chi_max 32 (order 64)."""
     from _circuits import entangling_circuit
     circ = entangling_circuit(14, 20, 6, 7, meas_every=6)
-    _, ores, _ = run_parity(B, circ, 64, "fp32", range(0, 6, 2), mode=(2, 128))
+    _, ores, _ = run_parity(B, circ, chi, "fp32", range(0, 6, 2), mode=(2, 128))
     assert max(o.max_bond for o in ores.values()) > 16
 
 
