@@ -720,6 +720,8 @@ __device__ void bargmax(double v, int i, double &vo, int &io, double *rv, int *r
 //     c = x y^H being replaced by (cs x - sg y, conj(sg) x + cs y),
 //     sg = sn c / |c|, where t = sn / cs is the root of smaller modulus of
 //     t^2 + 2 t (b - a) / 2|c| - 1 = 0, which makes the pair orthogonal.
+//     The squared row norms come from the rows at the start of a sweep and
+//     follow each rotation in closed form (a - t|c|, b + t|c|).
 //     Pairs with |c| > rot_tol sqrt(a b) are rotated; sweeps repeat until
 //     no pair had |c| > conv_tol sqrt(a b).  With rot_tol below conv_tol
 //     the last sweep leaves the rows orthogonal to rounding level: the
@@ -818,6 +820,21 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
     const int TPP = H <= NT / 16 ? 16 : kEigTpp, GP = NT / TPP;
     const int li = tid & (TPP - 1), gi = tid / TPP;
     for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
+      // squared row norms: from the rows at the start of each sweep, then
+      // updated in closed form by every rotation (a - tau |c|^2 and
+      // b + tau |c|^2, the new diagonal of the pair's 2 x 2 Gram); dg[k]
+      // holds row k's (free once the factor rows are final)
+      for (int i0 = 0; i0 < r; i0 += GP) {
+        const int i = i0 + gi;
+        double a = 0;
+        if (i < r) {
+          const c64 *X = G + (size_t)piv[i] * ld;
+          for (int j = li; j < nn; j += TPP) a += norm2(X[j]);
+        }
+        a = sumg(a, TPP);
+        if (i < r && li == 0) dg[i] = a;
+      }
+      __syncthreads();
       int rot = 0;
       for (int rnd = 0; rnd < P - 1; ++rnd) {
         for (int pi = gi; pi < H; pi += GP) {
@@ -829,7 +846,7 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
           if (p > q) { const int t = p; p = q; q = t; }
           if (q >= r) continue;
           c64 *X = G + (size_t)piv[p] * ld, *Y = G + (size_t)piv[q] * ld;
-          double a = 0, b = 0;
+          const double a = dg[p], b = dg[q];
           c64 cc = mk<double>(0, 0);
           // orders up to kEigRegN: the lane's elements of both rows stay in
           // registers between the products and the rotation
@@ -842,21 +859,10 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
               yr[u] = j < nn ? Y[j] : mk<double>(0, 0);
             }
 #pragma unroll
-            for (int u = 0; u < kEigRegN / kEigTpp; ++u) {
-              a += norm2(xr[u]);
-              b += norm2(yr[u]);
-              cc = cc + xr[u] * cj(yr[u]);
-            }
+            for (int u = 0; u < kEigRegN / kEigTpp; ++u) cc = cc + xr[u] * cj(yr[u]);
           } else {
-            for (int j = li; j < nn; j += TPP) {
-              const c64 xv = X[j], yv = Y[j];
-              a += norm2(xv);
-              b += norm2(yv);
-              cc = cc + xv * cj(yv);
-            }
+            for (int j = li; j < nn; j += TPP) cc = cc + X[j] * cj(Y[j]);
           }
-          a = sumg(a, TPP);
-          b = sumg(b, TPP);
           cc.x = sumg(cc.x, TPP);
           cc.y = sumg(cc.y, TPP);
           // in terms of h2 = |c|^2: t = tau |c|, cs = 1 / sqrt(1 + t^2),
@@ -883,6 +889,10 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
                 Y[j] = sgc * xv + cs * yv;
               }
             }
+            if (li == 0) {
+              dg[p] = a - tau * h2;
+              dg[q] = b + tau * h2;
+            }
             if (h2 > conv_tol * conv_tol * ab) rot = 1;
           }
         }
@@ -892,7 +902,7 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
       if (bsum<NT>(rot) == 0) break;
       if (sweeps == kEigMaxSweeps && tid == 0) atomicOr(err, STN_ERR_EIGEN);
     }
-    flops += (double)sweeps * (r * (r - 1) / 2) * 40.0 * nn;
+    flops += (double)sweeps * ((r * (r - 1) / 2) * 32.0 * nn + 4.0 * r * nn);
   }
   // 3. eigenvalues (squared row norms), their order, eigenvectors
   {
