@@ -239,7 +239,7 @@ def main():
         print(json.dumps({"copy_bytes": n, "read_bytes": n, "write_bytes": n}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(shots would shard across GPUs with one final gather).", file=sys.stderr)
         sys.exit(2)
 
