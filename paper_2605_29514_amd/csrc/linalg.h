@@ -819,7 +819,12 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
     const int P = r + (r & 1), H = P / 2;
     const int TPP = H <= NT / 16 ? 16 : kEigTpp, GP = NT / TPP;
     const int li = tid & (TPP - 1), gi = tid / TPP;
+    // "some pair of this sweep rotated by more than conv_tol", set by the
+    // rotating groups and read after the sweep's last barrier; two buffers
+    // alternate by sweep, so a reset never meets a read of the same buffer
+    __shared__ int rotf[2];
     for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
+      if (tid == 0) rotf[sweep & 1] = 0;
       // squared row norms: from the rows at the start of each sweep, then
       // updated in closed form by every rotation (a - tau |c|^2 and
       // b + tau |c|^2, the new diagonal of the pair's 2 x 2 Gram); dg[k]
@@ -835,7 +840,6 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
         if (i < r && li == 0) dg[i] = a;
       }
       __syncthreads();
-      int rot = 0;
       for (int rnd = 0; rnd < P - 1; ++rnd) {
         for (int pi = gi; pi < H; pi += GP) {
           // positions 1..P-1 shift by one per round (circle method), 0 stays
@@ -893,13 +897,13 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
               dg[p] = a - tau * h2;
               dg[q] = b + tau * h2;
             }
-            if (h2 > conv_tol * conv_tol * ab) rot = 1;
+            if (li == 0 && h2 > conv_tol * conv_tol * ab) rotf[sweep & 1] = 1;
           }
         }
         __syncthreads();
       }
       sweeps = sweep + 1;
-      if (bsum<NT>(rot) == 0) break;
+      if (rotf[sweep & 1] == 0) break;
       if (sweeps == kEigMaxSweeps && tid == 0) atomicOr(err, STN_ERR_EIGEN);
     }
     flops += (double)sweeps * ((r * (r - 1) / 2) * 32.0 * nn + 4.0 * r * nn);
