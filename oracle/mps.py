@@ -84,6 +84,10 @@ class MPS:
         # largest values but leaves ties at the cut open; a large value means the
         # kept subspace is ill-conditioned.
         self.max_cut_sensitivity = 0.0
+        # the same summed over every binding cut of the run: to first order each
+        # binding projector moves by rounding x its sensitivity, and the moves
+        # of successive cuts add at worst linearly
+        self.sum_cut_sensitivity = 0.0
         # margin of the chi decision at the relative cut: where more than
         # chi_max values exist, chi_max drops weight above the cut iff
         # s_chi^2 > eps sum s^2 (0-based index chi_max); the margin is
@@ -215,6 +219,7 @@ class MPS:
                 gap = float(s[k - 1] ** 2 - s[k] ** 2)
                 sens = float(s[k - 1] ** 2) / gap if gap > 0 else float("inf")
                 self.max_cut_sensitivity = max(self.max_cut_sensitivity, sens)
+                self.sum_cut_sensitivity += sens
             w = float(np.sum(s[k:].astype(np.float64) ** 2)) / tot if tot > 0 else 0.0
             self.discarded.append(w)
             self.fidelity *= (1.0 - w)

@@ -48,6 +48,7 @@ class ShotResult:
     bond_trace: List[int] = field(default_factory=list)    # max bond after each rotation
     pivot_events: int = 0
     cut_sensitivity: float = 0.0                            # worst binding cut (see MPS)
+    cut_sensitivity_sum: float = 0.0                        # summed over binding cuts (see MPS)
     flag_margin: float = float("inf")                       # closest chi decision to the eps cut (see MPS)
     tableau: Optional[InverseTableau] = None
     mps: Optional[MPS] = None
@@ -176,6 +177,7 @@ def run_shot(circ, shot: int, chi_max: int = 1 << 30, eps_cut: float = 0.0,
     st.res.trunc_err = 1.0 - st.mps.fidelity
     st.res.max_bond = max(st.mps.bonds() or [1])
     st.res.cut_sensitivity = st.mps.max_cut_sensitivity
+    st.res.cut_sensitivity_sum = st.mps.sum_cut_sensitivity
     st.res.flag_margin = st.mps.min_flag_margin
     st.res.tableau = st.tab
     st.res.mps = st.mps

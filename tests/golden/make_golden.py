@@ -8,6 +8,8 @@ Only formulas stated in the paper are evaluated here:
     event).
   * Eqs. (2)-(3): the depolarising channels pick each non-identity Pauli with
     probability p/3 (one qubit) and p/15 (two qubits).
+  * Table I: the error-rate ratios per location kind (single-qubit gate
+    0.1 p, two-qubit gate p, reset 2 p, measurement 5 p).
 """
 import json
 import math
@@ -23,7 +25,9 @@ def main():
     with open(os.path.join(HERE, "eq6_single_rotation.json"), "w") as f:
         json.dump(eq6, f, indent=1)
     dep = {"citation": "Eqs. (2)-(3): p/3 per single-qubit Pauli, p/15 per two-qubit Pauli pair",
-           "one_qubit": {"k": 3, "each": "p/3"}, "two_qubit": {"k": 15, "each": "p/15"}}
+           "one_qubit": {"k": 3, "each": "p/3"}, "two_qubit": {"k": 15, "each": "p/15"},
+           "table_I": {"citation": "Table I: error rates relative to the parameter p",
+                       "single_qubit_gate": 0.1, "two_qubit_gate": 1.0, "reset": 2.0, "measurement": 5.0}}
     with open(os.path.join(HERE, "eq2_eq3_depolarizing.json"), "w") as f:
         json.dump(dep, f, indent=1)
 
