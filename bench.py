@@ -1,31 +1,36 @@
 """Throughput benchmark of the STN crosstalk step on one MI355X.
 
-Workload: rotated surface code d=5 memory-Z experiment (49 qubits, 5
-syndrome rounds), ZZ crosstalk after each of the 4 CNOT layers on the 80
-nearest-neighbour pairs (theta ~ U[0.02, 0.10] per coupling) and the 72
-next-nearest pairs (own draw, halved), depolarising p = 1e-3 (Table I
-ratios), chi_max = 256, FP32 complex contractions with FP64 Gram, eigen-solve
-and norms, 1024 shots batched.  All inputs are seeded and synthetic and are
-resident in device memory before the timed region starts.
+Workload: rotated surface code d=5 memory-Z experiment (49 qubits),
+ZZ crosstalk after each of the 4 CNOT layers on the 80 nearest-neighbour
+pairs (theta ~ U[0.02, 0.10] per coupling) and the 72 next-nearest pairs
+(own draw, halved), depolarising p = 1e-3 (Table I ratios), chi_max = 256,
+FP32 complex contractions with FP64 Gram, eigen-solve and norms, 1024 shots
+batched.  All inputs are seeded and synthetic and are resident in device
+memory before the timed region starts.
 
-A step is one syndrome-extraction round over every shot: Clifford layers and
-noise (tableau), 608 crosstalk rotations (rewrite, bond-2 update, QR sweep,
-Gram/eigen truncation) and 24 ancilla measurements (projection, frame change,
-reset); the last round also reads out the data qubits.  --warmup W rounds run
-untimed first (they are the circuit's own first rounds), then --steps K rounds
-are timed.
+A step is one pass of the hot path over every shot from the initial state:
+stn_reset, syndrome round 1 (Clifford layers and noise on the tableau, 608
+crosstalk rotations -- rewrite, bond-2 update, compression and Gram/eigen
+truncation -- and 24 ancilla measurements with projection, frame change and
+reset), then round 2 up to and including its first crosstalk layer (152
+rotations), where the bonds grow from 16 to 64: 760 rotations per shot.  The
+circuit has only five rounds and a saturated round takes minutes, so the
+steps replay this window rather than walking on through the circuit.
+--warmup W steps run untimed, then --steps K steps are timed (HIP events on
+the library stream around all K).
 
-Prints one JSON line.  value = (shots x rotations in the timed rounds) / time.
+Prints one JSON line.  value = (shots x rotations per step x K) / time.
 roofline: the kernel class with the largest time in the timed region, its
-algorithmic work (counted on the device from the realised bond dimensions,
-in a replay of the same rounds: the counters slow the kernels they count)
-over its own launch time (HIP events on the library stream, timed pass).
-plain_fp64: the plain per-shot FP64 GPU form (per-step kernels, one shot at a
-time) of the same rounds on the first shots, with the batched records
-forced, within a time budget (--plain-seconds): its rotation rate and the
-largest relative difference of the batched FP32 probabilities from it.
-cpu_baseline: the FP64 oracle timed on the host cores over a bounded sample
-of the same rounds (see --cpu-seconds).
+algorithmic work per step (counted on the device from the realised bond
+dimensions in a separate replay of one step: the counters slow the kernels
+they count) over its own launch time in the timed region (HIP events around
+each of its launches on the library stream).  graph: the same step captured
+once as a HIP graph and replayed (time per replay, records bit-identical to
+the eager step).  plain_fp64: the plain per-shot FP64 GPU form (per-step
+kernels, one shot at a time) of the window on the first shots with the
+batched records forced, within a time budget, and the largest relative
+difference of the batched FP32 probabilities from it.  cpu_baseline: the
+FP64 oracle timed on the host cores over a bounded sample of the window.
 """
 from __future__ import annotations
 
@@ -60,6 +65,9 @@ CLASS_BOUND = {
     "tableau": ("hbm", "hbm_GBs"),
     "layer": ("alu", None),                 # fused layer kernel: mixed FP32 / FP64 work
 }
+# the machine's CPU share for one GPU: worker pools stay within it whatever the
+# host reports
+HOST_CPU_SHARE = 16
 
 
 def kernel_source_hash():
@@ -73,16 +81,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_class):
-    """HBM bytes per launch of a kernel class from the committed rocprofv3 PMC
-    summary (profiles/traffic_*.json), or None when no summary matches the
-    class or the kernel source changed since the counters were taken."""
+def measured_traffic(kernel_class, window):
+    """HBM bytes per launch of a kernel class on this window from the
+    committed rocprofv3 PMC summary (profiles/traffic_*.json), or None when
+    no summary matches or the kernel source changed since the counters were
+    taken."""
     import glob
     sha = kernel_source_hash()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
         with open(path) as f:
             t = json.load(f)
-        if t.get("kernel_class") == kernel_class and t.get("source_sha256_16") == sha:
+        if (t.get("kernel_class") == kernel_class and t.get("source_sha256_16") == sha
+                and t.get("window") == window):
             return float(t["traffic_bytes_per_launch"])
     return None
 
@@ -100,16 +110,41 @@ def split_rounds(ops):
     return bounds
 
 
+def window_stop(ops, window):
+    """End (exclusive) of the op window a step replays from the initial state."""
+    rounds = split_rounds(ops)
+    if window == "round1":
+        return rounds[0][1]
+    if window == "r2l1":
+        r2 = rounds[1][0]
+        return next(i for i in range(r2, len(ops)) if ops[i][0] == "rotate") + 1
+    raise ValueError(window)
+
+
+WINDOW_TEXT = {
+    "r2l1": "syndrome round 1 + round 2 through its first crosstalk layer",
+    "round1": "syndrome round 1",
+}
+
+
 def rotations_in(circ_ops, lo, hi):
     return sum(len(o[1]) for o in circ_ops[lo:hi] if o[0] == "rotate")
 
 
+def records_of(res):
+    import torch
+    if not res:
+        return None, None
+    return (torch.cat([r[0] for r in res], dim=1).cpu().numpy(),
+            torch.cat([r[1] for r in res], dim=1).cpu().numpy())
+
+
 # ----------------------------------------------------------------- CPU leg
 def _oracle_worker(args):
-    """Runs shots of the workload on the FP64 oracle, one after the other,
-    timing only the rotations of the timed rounds, until the time budget is
-    used; returns (rotations timed, seconds timed)."""
-    name, shots, shots_total, t_lo, t_hi, budget, chi, eps = args
+    """Runs shots of the workload on the FP64 oracle through the window, one
+    after the other, timing every rotation, until the time budget is used;
+    returns (rotations timed, seconds timed)."""
+    name, shots, shots_total, stop_op, budget, chi, eps = args
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import stn as ostn
     from paper_2605_29514_amd import workload
@@ -119,8 +154,9 @@ def _oracle_worker(args):
         if busy > budget:
             break
         st = ostn.Shot(circ.n, chi, eps)
-        for oi, op in enumerate(circ.ops[:t_hi]):
-            timed = oi >= t_lo
+        for op in circ.ops[:stop_op]:
+            if busy > budget:
+                break
             k = op["op"]
             if k == "gates":
                 for g in op["gates"]:
@@ -131,67 +167,22 @@ def _oracle_worker(args):
                 for ri, qs in enumerate(op["paulis"]):
                     t0 = time.perf_counter()
                     st.rotate([int(q) for q in qs], float(op["theta"][shot, ri]))
-                    if timed:
-                        busy += time.perf_counter() - t0
-                        done += 1
+                    busy += time.perf_counter() - t0
+                    done += 1
+                    if busy > budget:
+                        break
             elif k == "measure":
                 for mj, q in enumerate(op["qubits"]):
                     st.measure(int(q), float(op["u"][shot, mj]), None, bool(op["reset"]))
     return done, busy
 
 
-def plain_fp64_form(circ, chi, rounds, W, K, batched, n, dev, budget_s):
-    """The plain per-shot FP64 GPU form of the same rounds: per-step kernels,
-    one shot at a time, FP64 throughout, on up to the first n shots with the
-    batched run's records forced, until budget_s seconds are spent (at least
-    one timed round).  Returns its rotation rate over the timed rounds it ran
-    and the largest relative difference of the batched FP32 probabilities
-    from it over the measurements it ran."""
-    import torch
-    from paper_2605_29514_amd import stn
-    rec = torch.cat([r[0] for r in batched], dim=1)[:n].cpu().numpy()
-    prob = torch.cat([r[1] for r in batched], dim=1)[:n].cpu().numpy()
-    full = np.zeros((n, circ.n_measurements), np.uint8)
-    full[:, :rec.shape[1]] = rec
-    ms_total, rot_total, worst, shots_used = 0.0, 0, 0.0, 0
-    t_start = time.perf_counter()
-    for s in range(n):
-        c1 = circ.shot_slice(s, s + 1)
-        sim = stn.Simulator(c1.n, 1, chi, "fp64", None, dev, layer_mode=1)
-        ops1 = stn.prepare(c1, dev, forced=full[s:s + 1])
-        r1 = split_rounds(ops1)
-        res = []
-        for r in range(W + K):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(sim.stream)
-            stn.run_prepared(sim, ops1, *r1[r], records=res)
-            b.record(sim.stream)
-            sim.sync()
-            if r >= W:
-                ms_total += a.elapsed_time(b)
-                rot_total += rotations_in(ops1, *r1[r])
-            print(f"# plain FP64 form: shot {s + 1}, round {r + 1} done", file=sys.stderr, flush=True)
-            if r >= W and time.perf_counter() - t_start > budget_s:
-                break
-        p64 = torch.cat([x[1] for x in res], dim=1).cpu().numpy()[0]
-        worst = max(worst, float(np.max(np.abs(prob[s, :p64.shape[0]] - p64) / p64)))
-        shots_used += 1
-        del sim
-        if time.perf_counter() - t_start > budget_s:
-            break
-    return {"value": rot_total / (ms_total / 1e3), "unit": "rotations/s", "shots": shots_used,
-            "timed_rotations": rot_total, "per_step_kernels": True, "precision": "fp64",
-            "max_rel_prob_diff_batched_fp32": worst}
-
-
-def cpu_baseline(name, circ, ops_bounds, t_lo_round, t_hi_round, chi, eps, budget, cores):
-    """Oracle rotations/s over the same rounds: `cores` worker processes (BLAS
-    1 thread each) take shots 0, 1, 2, ... round-robin and time the
-    rotations of the timed rounds until each has spent `budget` seconds."""
-    # prepared ops mirror the circuit ops one to one
-    t_lo, t_hi = ops_bounds[t_lo_round][0], ops_bounds[t_hi_round - 1][1]
+def cpu_baseline(name, circ, stop_op, chi, eps, budget, cores):
+    """Oracle rotations/s over the window: `cores` worker processes (BLAS 1
+    thread each) take shots 0, 1, 2, ... round-robin and time every rotation
+    until each has spent `budget` seconds."""
     per = [list(range(w, circ.n_shots, cores)) for w in range(cores)]
-    args = [(name, per[w], circ.n_shots, t_lo, t_hi, budget, chi, eps) for w in range(cores)]
+    args = [(name, per[w], circ.n_shots, stop_op, budget, chi, eps) for w in range(cores)]
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -201,30 +192,111 @@ def cpu_baseline(name, circ, ops_bounds, t_lo_round, t_hi_round, chi, eps, budge
     busy = max(r[1] for r in res)
     return {"value": done / busy if busy > 0 else 0.0, "unit": "rotations/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{cores} worker processes (FP64 numpy oracle, BLAS 1 thread each) taking shots "
-                      f"round-robin, each timing the rotations of the timed rounds until {budget:.0f} s were "
-                      f"spent; {done} rotations, slowest worker {busy:.1f} s (wall incl. replays {wall:.1f} s)"}
+            "sample": f"{cores} worker processes (FP64 numpy oracle, BLAS 1 thread each), each running its "
+                      f"shots (round-robin from shot 0) through the window from the start and timing every "
+                      f"rotation until {budget:.0f} s were spent; {done} rotations in total, slowest worker "
+                      f"{busy:.1f} s (wall {wall:.1f} s).  Each worker covers round 1 and the first "
+                      f"rotations of round 2, where the per-rotation cost is lower than later in the "
+                      f"window, so the rate overstates the oracle on the whole window"}
+
+
+def plain_fp64_form(circ, chi, stop_op, rec, prob, n, dev, budget_s):
+    """The plain per-shot FP64 GPU form of the window: per-step kernels, one
+    shot at a time, FP64 throughout, on up to the first n shots with the
+    batched run's records forced, op by op until budget_s seconds are spent.
+    Returns its rotation rate over the rotation ops it ran and the largest
+    relative difference of the batched FP32 probabilities from it."""
+    import torch
+    from paper_2605_29514_amd import stn
+    full = np.zeros((n, circ.n_measurements), np.uint8)
+    full[:, :rec.shape[1]] = rec[:n]
+    ms_total, rot_total, worst, shots_used = 0.0, 0, 0.0, 0
+    t_start = time.perf_counter()
+    for s in range(n):
+        c1 = circ.shot_slice(s, s + 1)
+        sim = stn.Simulator(c1.n, 1, chi, "fp64", None, dev, layer_mode=1)
+        ops1 = stn.prepare(c1, dev, forced=full[s:s + 1])
+        res = []
+        for i in range(stop_op):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(sim.stream)
+            stn.run_prepared(sim, ops1, i, i + 1, records=res)
+            b.record(sim.stream)
+            sim.sync()
+            if ops1[i][0] == "rotate":
+                ms_total += a.elapsed_time(b)
+                rot_total += len(ops1[i][1])
+                print(f"# plain FP64 form: shot {s + 1}, op {i + 1}/{stop_op}", file=sys.stderr, flush=True)
+            if time.perf_counter() - t_start > budget_s:
+                break
+        if res:
+            p64 = torch.cat([x[1] for x in res], dim=1).cpu().numpy()[0]
+            worst = max(worst, float(np.max(np.abs(prob[s, :p64.shape[0]] - p64) / p64)))
+        shots_used += 1
+        del sim
+        if time.perf_counter() - t_start > budget_s:
+            break
+    return {"value": rot_total / (ms_total / 1e3) if ms_total else None, "unit": "rotations/s",
+            "shots": shots_used, "timed_rotations": rot_total, "per_step_kernels": True, "precision": "fp64",
+            "max_rel_prob_diff_batched_fp32": worst}
+
+
+def graph_leg(args, circ, chi, prec, eps, dev, ops_stop, tuned, ref_rec, ref_prob, reps=1):
+    """Captures stn_reset + the window once on a side stream and replays it;
+    returns the time per replay and whether the records and probabilities
+    equal the eager step's."""
+    import torch
+    from paper_2605_29514_amd import stn
+    side = torch.cuda.Stream()
+    sim = stn.Simulator(circ.n, circ.n_shots, chi, prec, eps, dev, layer_mode=tuned[0],
+                        layer_threads=tuned[1], layer_lds=tuned[2], stream=side)
+    ops = stn.prepare(circ, dev)[:ops_stop]
+    t0 = time.perf_counter()
+    graph, res = stn.capture(sim, ops)
+    cap_s = time.perf_counter() - t0
+    times = []
+    same = True
+    for _ in range(reps):
+        side.wait_stream(torch.cuda.current_stream())
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(side):             # a replay goes to the current stream
+            a.record(side)
+            graph.replay()
+            b.record(side)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+        rec, prob = records_of(res)
+        same = same and bool(np.array_equal(rec, ref_rec) and np.array_equal(prob, ref_prob))
+        print(f"# graph replay {len(times)}: {times[-1]:.1f} ms", file=sys.stderr, flush=True)
+    del graph, res, sim
+    torch.cuda.synchronize()
+    return {"ms_per_replay": float(np.mean(times)), "capture_s": cap_s, "replays": reps,
+            "bit_identical_to_eager": same}
 
 
 # ----------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="d5_nnn_chi256")
+    ap.add_argument("--window", default="r2l1", choices=sorted(WINDOW_TEXT))
     ap.add_argument("--shots", type=int, default=None, help="override the shot count (testing only)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-all", action="store_true")
     ap.add_argument("--layer-mode", type=int, default=0, help="0 automatic, 1 per-step kernels, 2 fused")
     ap.add_argument("--layer-threads", type=int, default=0, help="threads per shot of the fused kernel")
+    ap.add_argument("--layer-lds", type=int, default=0, help="eigen-solve LDS order of the fused kernel")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the step")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-shot FP64 GPU form (per-step kernels, one shot at a time)")
-    ap.add_argument("--plain-shots", type=int, default=8)
-    ap.add_argument("--plain-seconds", type=float, default=60.0,
-                    help="time budget of the plain FP64 form (whole rounds; at least one)")
+    ap.add_argument("--plain-shots", type=int, default=4)
+    ap.add_argument("--plain-seconds", type=float, default=45.0,
+                    help="time budget of the plain FP64 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -239,8 +311,8 @@ def main():
         print(json.dumps({"copy_bytes": n, "read_bytes": n, "write_bytes": n}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path "
-              "(shots would shard across GPUs with one final gather).", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (shots would shard "
+              "across GPUs with one final gather of records, log P and truncation errors).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -252,94 +324,85 @@ def main():
     chi, prec = opts["chi_max"], opts["precision"]
     eps = stn.DEFAULT_EPS[stn.STN_FP64 if prec == "fp64" else stn.STN_FP32]
     dev = "cuda:0"
-    print(f"# building inputs: {args.config} shots={circ.n_shots}", file=sys.stderr, flush=True)
+    print(f"# building inputs: {args.config} shots={circ.n_shots} window {args.window}", file=sys.stderr, flush=True)
     sim = stn.Simulator(circ.n, circ.n_shots, chi, prec, eps, dev, layer_mode=args.layer_mode,
-                        layer_threads=args.layer_threads)
+                        layer_threads=args.layer_threads, layer_lds=args.layer_lds)
     ops = stn.prepare(circ, dev)
-    rounds = split_rounds(ops)
-    schedule = {"layer_mode": args.layer_mode, "layer_threads": args.layer_threads, "tuned": False}
-    W, K = args.warmup, args.steps
-    if args.layer_mode == 0 and args.layer_threads == 0 and not args.no_tune and W + K <= len(rounds):
+    stop = window_stop(ops, args.window)
+    rot_per_shot = rotations_in(ops, 0, stop)
+    W, K = max(0, args.warmup), max(1, args.steps)
+    chosen = (args.layer_mode or 2, args.layer_threads or 128, args.layer_lds)
+    schedule = {"layer_mode": chosen[0], "layer_threads": chosen[1], "layer_lds": chosen[2], "tuned": False}
+    if args.layer_mode == 0 and args.layer_threads == 0 and not args.no_tune:
         from paper_2605_29514_amd import tune
-        # tuning window: with one timed round, that whole round (its early
-        # layers, where bonds are small, favour other block sizes than the
-        # rest); with several, the first two crosstalk layers of the second
-        # timed round (saturated rounds cost the most, a whole one per
-        # candidate would take minutes).  Reached once, restored from a
-        # checkpoint per candidate when that fits in memory.
-        r0 = W + 1 if K >= 2 else W
-        start = rounds[r0][0]
-        if start > 0 and sim.lib.stn_checkpoint_bytes(sim.ctx) > (16 << 30):
-            start = 0
-        stop = rounds[r0][1] if K == 1 else tune.layers_stop(ops, 2, start)
         key = tune.problem_key(torch.cuda.get_device_name(0), circ.n, circ.n_shots, chi, prec, args.config)
-        t = tune.autotune(sim, ops, stop, start=start, key=f"{key}|window@{start}:{stop}",
+        # the fused shapes only: at this shot count the per-step schedule is
+        # slower by orders of magnitude; each candidate runs one whole step
+        t = tune.autotune(sim, ops, stop, key=f"{key}|window {args.window}", candidates=tune.FUSED,
                           log=lambda m: print("# " + m, file=sys.stderr, flush=True))
-        schedule = {"layer_mode": t["choice"][0], "layer_threads": t["choice"][1], "tuned": True,
-                    "cached": t["cached"], "candidates_ms": t["ms"], "tuning_window_ops": [start, stop]}
-        print(f"# autotuned schedule {t['choice']}", file=sys.stderr, flush=True)
-    if W + K > len(rounds):
-        print(f"warmup + steps exceeds the {len(rounds)} rounds of the circuit", file=sys.stderr)
-        sys.exit(2)
+        chosen = tuple(t["choice"])
+        schedule = {"layer_mode": chosen[0], "layer_threads": chosen[1], "layer_lds": chosen[2], "tuned": True,
+                    "cached": t["cached"], "candidates_ms": t["ms"]}
+        print(f"# autotuned schedule {chosen}", file=sys.stderr, flush=True)
+    else:
+        stn_mode = args.layer_mode
+        if stn_mode:
+            sim.set_layer_mode(stn_mode)
     torch.cuda.synchronize()
-    batched = []                      # (outcomes, prob) device tensors of every measurement op run
-    for r in range(W):
+    for w in range(W):
         t = time.perf_counter()
-        stn.run_prepared(sim, ops, *rounds[r], records=batched)
+        sim.reset()
+        stn.run_prepared(sim, ops, 0, stop)
         sim.sync()
-        print(f"# warmup round {r + 1}: {time.perf_counter() - t:.2f} s, max bond "
-              f"{int(sim.bonds().max())}", file=sys.stderr, flush=True)
+        print(f"# warmup step {w + 1}: {time.perf_counter() - t:.2f} s, max bond {int(sim.bonds().max())}",
+              file=sys.stderr, flush=True)
     # Timed region: launch events per kernel class only.  The device work
     # counters (atomics from every block, per-phase clocks) slow the kernels
-    # they count, so the work per launch comes from a counted replay below.
-    prof_classes = None if args.profile_all else ["eigen", "qr", "gemm", "gram", "layer"]
+    # they count, so the work per step comes from a counted replay below.
+    prof_classes = None if args.profile_all else ["eigen", "qr", "gemm", "gram", "layer", "expect"]
     sim.profile(prof_classes, counters=False)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(sim.stream)
-    round_ev = []
-    for r in range(W, W + K):
-        stn.run_prepared(sim, ops, *rounds[r], records=batched)
-        round_ev.append(torch.cuda.Event())
-        round_ev[-1].record(sim.stream)
-    ev1.record(sim.stream)
-    # progress: poll the per-round events (host side only; the GPU timeline
-    # is what ev0 / ev1 measure)
-    for i, e in enumerate(round_ev):
+    last = []
+    for k in range(K):
+        last = []
+        sim.reset()
+        stn.run_prepared(sim, ops, 0, stop, records=last)
+        e = torch.cuda.Event()
+        e.record(sim.stream)
+        # progress (host side only; the GPU timeline is what ev0 / ev1 measure)
         while not e.query():
-            time.sleep(0.05)
-        print(f"# timed round {W + i + 1} done at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+            time.sleep(0.02)
+        print(f"# timed step {k + 1} done at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    ev1.record(sim.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
     sim.sync()
     prof = sim.profile_read()
-    lo, hi = rounds[W][0], rounds[W + K - 1][1]
-    n_rot = rotations_in(ops, lo, hi) * circ.n_shots
     bonds = sim.bonds()
+    rec, prob = records_of(last)
+    n_rot = rot_per_shot * circ.n_shots * K
     value = n_rot / (ms / 1e3)
-    # counted replay of the same rounds from the initial state (deterministic:
-    # same launches, same bonds): algorithmic work per class, phase shares
-    sim.profile([])
-    sim.reset()
-    for r in range(W):
-        stn.run_prepared(sim, ops, *rounds[r])
+    # counted replay of one step (deterministic: same launches, same bonds):
+    # algorithmic work per class, phase shares and branch counts
     sim.profile(prof_classes, counters=True)
-    for r in range(W, W + K):
-        stn.run_prepared(sim, ops, *rounds[r])
-        sim.sync()
-        print(f"# counted replay of round {r + 1} done", file=sys.stderr, flush=True)
+    sim.reset()
+    stn.run_prepared(sim, ops, 0, stop)
+    sim.sync()
     work = sim.profile_read()
     phases = sim.profile_phases()
+    paths = sim.profile_paths()
     sim.profile([])
+    print("# counted replay done", file=sys.stderr, flush=True)
     for c in stn.K_CLASSES:
-        prof[c]["flops"], prof[c]["bytes"] = work[c]["flops"], work[c]["bytes"]
-        if work[c]["launches"] != prof[c]["launches"]:
-            print(f"# warning: class {c}: {prof[c]['launches']} timed launches, {work[c]['launches']} counted",
-                  file=sys.stderr, flush=True)
-    prof["layer_fp64_flops"], prof["eigen_sweeps"] = work["layer_fp64_flops"], work["eigen_sweeps"]
-    # dominant kernel class by measured time
+        prof[c]["flops"], prof[c]["bytes"] = work[c]["flops"] * K, work[c]["bytes"] * K
+        if work[c]["launches"] * K != prof[c]["launches"]:
+            print(f"# warning: class {c}: {prof[c]['launches']} timed launches, {work[c]['launches']} per "
+                  f"counted step", file=sys.stderr, flush=True)
+    prof["layer_fp64_flops"], prof["eigen_sweeps"] = work["layer_fp64_flops"] * K, work["eigen_sweeps"]
     classes = [c for c in stn.K_CLASSES if prof[c]["launches"] > 0]
     dom = max(classes, key=lambda c: prof[c]["ms"]) if classes else None
     roof = None
@@ -356,44 +419,59 @@ def main():
             achieved = d["flops"] / (d["ms"] / 1e3) / 1e12
             unit = "TFLOP/s"
         peak = PEAKS[peak_key]
-        if dom == "layer" and prec == "fp32" and d["flops"] > 0:
+        if dom in ("layer", "expect") and prec == "fp32" and d["flops"] > 0 and dom == "layer":
             # FP64 Gram + eigen-solve at the FP64 peak, the rest at the FP32 peak
             f64 = prof["layer_fp64_flops"]
             f32 = d["flops"] - f64
             peak = d["flops"] / (f32 / PEAKS["fp32_vector_TFs"] + f64 / PEAKS["fp64_vector_TFs"])
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": measured_traffic(dom), "kernel_class": dom,
+                "frac": achieved / peak, "traffic": measured_traffic(dom, args.window), "kernel_class": dom,
                 "launches": d["launches"], "avg_launch_ms": per_launch_ms,
                 "algorithmic_flops_per_launch": d["flops"] / d["launches"],
                 "fp64_flops_share": (prof["layer_fp64_flops"] / d["flops"]) if dom == "layer" and d["flops"] else None,
                 "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
                 "share_of_step_time": d["ms"] / ms if ms > 0 else None}
+    graph = None
+    if not args.no_graph:
+        del sim
+        torch.cuda.synchronize()
+        graph = graph_leg(args, circ, chi, prec, eps, dev, stop, chosen, rec, prob)
     plain = None
     if not args.no_plain and prec == "fp32":
-        plain = plain_fp64_form(circ, chi, rounds, W, K, batched, min(args.plain_shots, circ.n_shots), dev,
+        plain = plain_fp64_form(circ, chi, stop, rec, prob, min(args.plain_shots, circ.n_shots), dev,
                                 args.plain_seconds)
-        plain["batched_fp32_speedup"] = value / plain["value"]
+        if plain["value"]:
+            plain["batched_fp32_speedup"] = value / plain["value"]
     cpu = None
     if not args.no_cpu:
-        cores = min(os.cpu_count() or 1, 16)
-        print(f"# cpu baseline on {cores} cores", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.config, circ, rounds, W, W + K, chi, eps,
-                           args.cpu_seconds, cores)
+        try:
+            avail = len(os.sched_getaffinity(0))
+        except AttributeError:
+            avail = os.cpu_count() or 1
+        cores = max(1, min(avail, HOST_CPU_SHARE))
+        print(f"# cpu baseline on {cores} cores ({avail} available to this process)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.config, circ, stop, chi, eps, args.cpu_seconds, cores)
+    ph_tot = sum(phases.values())
     out = {
         "metric": f"crosstalk rotations/sec (shots x gates) at d={cfg['d']}, chi={chi}",
         "value": value, "unit": "rotations/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 contractions + f64 gram/eigen/norms" if prec == "fp32" else "c128",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: rotated surface code d={cfg['d']} memory-Z, "
-                               f"{circ.n} qubits, rounds {W + 1}-{W + K} of {cfg['rounds']}",
-                   "shots": circ.n_shots, "chi_max": chi, "rotations_timed": n_rot,
+        "config": {"workload": f"{args.config}: rotated surface code d={cfg['d']} memory-Z, {circ.n} qubits, "
+                               f"{circ.n_shots} shots; step = stn_reset + {WINDOW_TEXT[args.window]} "
+                               f"({rot_per_shot} rotations per shot); bonds after the step: max "
+                               f"{int(bonds.max())}, mean {float(bonds.mean()):.1f}",
+                   "window": args.window, "shots": circ.n_shots, "chi_max": chi,
+                   "rotations_per_step": rot_per_shot * circ.n_shots,
                    "max_bond_after": int(bonds.max()), "mean_bond_after": float(bonds.mean()),
-                   "wall_s": wall, "eigen_sweeps": prof["eigen_sweeps"], "schedule": schedule,
+                   "fp32_cut": eps, "wall_s": wall, "eigen_sweeps_per_step": prof["eigen_sweeps"],
+                   "schedule": schedule,
                    "class_ms": {c: prof[c]["ms"] for c in classes},
-                   "layer_phase_share": ({k: v / sum(phases.values()) for k, v in phases.items()}
-                                         if sum(phases.values()) > 0 else None)},
+                   "layer_phase_share": ({k: v / ph_tot for k, v in phases.items()} if ph_tot > 0 else None),
+                   "layer_branches_per_step": paths},
         "roofline": roof,
+        "graph": graph,
         "plain_fp64": plain,
         "cpu_baseline": cpu,
     }

@@ -60,7 +60,7 @@ enum { STN_FP64 = 0,   /* complex128 everywhere */
 typedef struct {
     int n_qubits;        /* chain length n, 1..1024 */
     int n_shots;         /* independent shots simulated together, >= 1 */
-    int chi_max;         /* bond-dimension cap (Sec. IV.B), 1..512 */
+    int chi_max;         /* bond-dimension cap (Sec. IV.B), 1..1024 */
     int precision;       /* STN_FP64 or STN_FP32 */
     double eps_cut;      /* drop Schmidt values with lambda^2 <= eps_cut * sum lambda^2
                             (Eq. 8).  The squared values come from an FP64 Gram
@@ -184,6 +184,18 @@ stn_status stn_reset(stn_ctx *ctx);
  * recorded outcomes forced, stn_tape_end, stn_backward.  The adjoint state
  * carries over between stretches (stn_adjoint_zero before the last one). */
 
+/* Squared Schmidt values across the cut between sites bond-1 and bond
+ * (1 <= bond <= n_qubits-1) for every shot: the lambda_i^2 of Eq. 8 that
+ * the truncation keeps or drops there (the Fig. 2 spectrum), normalised to
+ * sum 1 and in descending order, from an FP64 Gram of the centre tensor and
+ * a two-sided Jacobi eigen-solve on the device.  dev_out: double
+ * [n_shots][ld] (caller-owned; entries past a shot's bond dimension set to
+ * 0); ld must be at least min(chi_max, 2^min(bond, n-bond)).  dev_rank:
+ * int32 [n_shots] (may be NULL) receives the bond dimension at the cut.
+ * Moves the orthogonality centre to site `bond` (the state is unchanged).
+ * STN_ESTATE while a tape is recording. */
+stn_status stn_spectrum(stn_ctx *ctx, int bond, double *dev_out, int ld, int *dev_rank);
+
 /* Device bytes of a tape of up to max_steps rotations + measurements (each
  * step keeps a snapshot of all shots' MPS slots).  0 for bad arguments. */
 size_t stn_tape_bytes(const stn_ctx *ctx, int max_steps);
@@ -279,6 +291,22 @@ stn_status stn_profile_read(stn_ctx *ctx, double *host_ms, double *host_flops,
  * Synchronises. */
 stn_status stn_profile_phases(stn_ctx *ctx, double *host_cycles);
 
+/* Branch counters of the fused layer kernel while profiling is on with
+ * counters (stn_profile without STN_PROFILE_TIMING_ONLY), summed over shots
+ * since the last stn_profile call; host_counts: 8 doubles, in order:
+ *  0 two-term steps whose left-to-right sweep formed left-environment Grams,
+ *  1 steps that took the Householder QR sweep instead (a doubled bond of the
+ *    span above the environment limit),
+ *  2 truncation eigen-solves with the matrix in LDS,
+ *  3 eigen-solves of order up to 128 with the matrix in global scratch,
+ *  4 eigen-solves of order above 128,
+ *  5 the largest eigen-solve order seen,
+ *  6 shader cycles spent in the pivoted Cholesky of the FP32-path solves
+ *    (part of phase 6 of stn_profile_phases),
+ *  7 FP64-path two-sided Jacobi solves with the matrix in global scratch.
+ * Synchronises. */
+stn_status stn_profile_paths(stn_ctx *ctx, double *host_counts);
+
 /* How stn_rotate schedules its kernels: 1 = one launch per kernel step for
  * all shots (grids spread each product over many blocks; best for few
  * shots), 2 = one launch per chunk of up to 64 rotations in which each block
@@ -290,6 +318,21 @@ stn_status stn_set_layer_mode(stn_ctx *ctx, int mode);
  * 128 (the default) or 256.  A tuning knob: results agree to rounding order.
  * STN_EINVAL for any other value. */
 stn_status stn_set_layer_threads(stn_ctx *ctx, int threads);
+
+/* Largest doubled bond at which the fused layer kernel's left-to-right
+ * sweep forms left-environment Grams instead of Householder QR (0: always
+ * QR).  stn_init sets the largest its workspace allows (up to 256); values
+ * above that are STN_EINVAL.  A tuning knob: results agree to rounding
+ * order. */
+stn_status stn_set_layer_env(stn_ctx *ctx, int max_bond);
+
+/* LDS tile of the fused layer kernel's FP32-path eigen-solve: truncation
+ * steps of order up to `order` (32 or 64) keep the factor in LDS (larger ones
+ * use the shot's global scratch); 0 = chosen from chi_max (64 when
+ * 17 <= chi_max <= 32, else 32).  The 64 tile takes ~70 KB of LDS per block,
+ * so fewer shots are resident per compute unit.  A tuning knob: results
+ * agree to rounding order.  STN_EINVAL for any other value. */
+stn_status stn_set_layer_lds(stn_ctx *ctx, int order);
 
 /* Overwrite one MPS site tensor of one shot from the host (synchronises):
  * host_buf holds dl*2*dr complex elements in the layout of stn_get_site; the
@@ -306,6 +349,30 @@ stn_status stn_set_center(stn_ctx *ctx, int center);
 /* Orthogonality centre site shared by all shots (sites left of it are
  * left-orthonormal, right of it right-orthonormal). */
 int stn_center(const stn_ctx *ctx);
+
+/* ------------------------------------------------------------ decoding
+ * Union-find decoder of detection events (host code; the paper decodes by
+ * minimum-weight matching over the Pauli-twirled error model, Sec. III.D).
+ * A detector graph: n_nodes detectors 0..n_nodes-1 plus the boundary, whose
+ * index is n_nodes; each edge is one independent error mechanism that fires
+ * detectors a and b (b = n_nodes: one detector and the boundary), with
+ * weight log((1 - p) / p) > 0 and obs = 1 when it flips the logical
+ * observable.  Per shot, events[s * n_nodes + v] = 1 when detector v fired.
+ * pred[s] receives the predicted observable flip (parity of the flagged
+ * edges of the correction); corrections (may be NULL) receives the
+ * correction as uint8 [n_shots][n_edges].  The correction fires exactly the
+ * detectors that fired.  All pointers are host memory; no GPU is used.
+ * STN_EINVAL on an edge out of range, a loop, or a weight that is not
+ * positive and finite. */
+typedef struct {
+    int32_t a, b;        /* detector indices; n_nodes = the boundary */
+    double weight;       /* log((1 - p) / p) of the mechanism */
+    uint8_t obs;         /* 1: flips the logical observable */
+    uint8_t pad[7];
+} stn_dem_edge;
+
+stn_status stn_decode(const stn_dem_edge *edges, int n_edges, int n_nodes, const uint8_t *events,
+                      int n_shots, uint8_t *pred, uint8_t *corrections);
 
 #ifdef __cplusplus
 }

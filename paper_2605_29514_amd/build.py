@@ -2,9 +2,10 @@
 
     python -m paper_2605_29514_amd.build          # or build() from Python
 
-Every HIP translation unit is compiled with hipcc for gfx950 with packed
-FP32 instructions disabled, then linked into one shared library with a plain
-C ABI (include/stn.h).
+Every translation unit (the HIP kernels and their host side, and the
+host-only decoder) is compiled with hipcc for gfx950 with packed FP32
+instructions disabled, then linked into one shared library with a plain C
+ABI (include/stn.h).
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstn.so")
-SOURCES = ["api.hip", "tableau.hip", "mps.hip", "layer.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "tableau.hip", "mps.hip", "layer.hip", "adjoint.hip", "decode.cpp"]
 ARCH = "gfx950"
 
 
@@ -44,7 +45,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -53,7 +54,7 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]

@@ -125,6 +125,8 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 thread_local Prof *g_prof = nullptr;
 
+
+
 hipEvent_t Prof::get() {
   if (used == pool.size()) {
     hipEvent_t e;
@@ -237,8 +239,13 @@ void plan_mps(Layout &L, int n, int S, int chi, size_t esz, int wmul, char *base
   size_t o_J = L.off((size_t)Jcap * S);
   // environment path of the fused kernel (forward state only): one Gram per
   // site of a span for doubled bonds up to eb
+  // doubled bonds up to eb (the product scratch F = E B is eb x 2 eb); the
+  // packed Grams of a span share a store of n x ec^2 per shot, ec halved
+  // (down to 32) until every shot's store fits the memory budget
   const int64_t eb = wmul == 2 ? std::min<int64_t>(kEnvBond, 2 * chi_eff) : 0;
-  const int64_t Escap = (int64_t)n * eb * eb, Fscap = eb * 2 * eb;
+  int64_t ec = std::min<int64_t>(eb, kEnvStore);
+  while (ec > 32 && (size_t)S * n * ec * ec * sizeof(c64) > kEnvBudget) ec /= 2;
+  const int64_t Escap = (int64_t)n * ec * ec, Fscap = eb * 2 * eb;
   size_t o_Es = L.off((size_t)Escap * S * sizeof(c64)), o_Fs = L.off((size_t)Fscap * S * sizeof(c64));
   if (base) {
     MpsDev &m = *mp;
@@ -260,6 +267,7 @@ void plan_mps(Layout &L, int n, int S, int chi, size_t esz, int wmul, char *base
     m.Es = (c64 *)(base + o_Es); m.Es_cap = Escap;
     m.Fs = (c64 *)(base + o_Fs); m.Fs_cap = Fscap;
     m.ebond = (int)eb;
+    m.ebond_alloc = (int)eb;
     m.logp = (double *)(base + o_logp); m.fid = (double *)(base + o_fid);
     m.p0 = (double *)(base + o_p0); m.nrm = (double *)(base + o_nrm);
     m.pm = (double *)(base + o_pm); m.trunc = (int *)(base + o_tr);
@@ -267,6 +275,7 @@ void plan_mps(Layout &L, int n, int S, int chi, size_t esz, int wmul, char *base
     m.wmul = wmul;
     m.keep_norm = 0;
     m.prof = 0;
+    m.lds_order = 0;
   }
   if (offs) {
     offs->clear();
@@ -321,7 +330,7 @@ size_t plan(const stn_config &c, stn_ctx *ctx, char *base, std::vector<int64_t> 
 
 bool valid(const stn_config *c) {
   return c && c->n_qubits >= 1 && c->n_qubits <= 1024 && c->n_shots >= 1 && c->chi_max >= 1 &&
-         c->chi_max <= 512 && (c->precision == STN_FP64 || c->precision == STN_FP32) &&
+         c->chi_max <= 1024 && (c->precision == STN_FP64 || c->precision == STN_FP32) &&
          c->eps_cut >= 0 && c->eps_cut < 1;
 }
 
@@ -1006,6 +1015,21 @@ stn_status stn_profile_phases(stn_ctx *c, double *cycles) {
   return e == hipSuccess ? STN_OK : fail(c, STN_EDEVICE, hipGetErrorString(e));
 }
 
+stn_status stn_profile_paths(stn_ctx *c, double *counts) {
+  if (!c || !counts) return STN_EINVAL;
+  stn_status s = sync_status(c);
+  if (s != STN_OK) return s;
+  double w[kPaths];
+  hipError_t e = hipMemcpy(w, c->mps.work + kPathBase, kPaths * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, STN_EDEVICE, hipGetErrorString(e));
+  for (int i = 0; i < kPaths; ++i) counts[i] = w[i];
+  // the largest order is kept as an integer (atomicMax on its bits)
+  unsigned long long mo;
+  std::memcpy(&mo, &w[kPathMaxOrder], 8);
+  counts[kPathMaxOrder] = (double)mo;
+  return STN_OK;
+}
+
 stn_status stn_set_layer_mode(stn_ctx *c, int mode) {
   if (!c || mode < 0 || mode > 2) return STN_EINVAL;
   c->layer_mode = mode;
@@ -1015,6 +1039,33 @@ stn_status stn_set_layer_mode(stn_ctx *c, int mode) {
 stn_status stn_set_layer_threads(stn_ctx *c, int threads) {
   if (!c || (threads != 64 && threads != 128 && threads != 256)) return STN_EINVAL;
   c->layer_threads = threads;
+  return STN_OK;
+}
+
+stn_status stn_spectrum(stn_ctx *c, int bond, double *dev_out, int ld, int *dev_rank) {
+  if (!c || !dev_out || bond < 1 || bond > c->n - 1) return STN_EINVAL;
+  if (ld < dmax_h(c->n, c->chi, bond)) return fail(c, STN_EINVAL, "spectrum row shorter than the largest bond");
+  if (c->taping) return fail(c, STN_ESTATE, "spectrum while recording a tape");
+  ProfScope ps(c);
+  if (c->prec == STN_FP64) {
+    move_center_into<double>(c, bond, bond);
+    mps_spectrum<double>(c->mps, bond, dev_out, ld, dev_rank, c->st);
+  } else {
+    move_center_into<float>(c, bond, bond);
+    mps_spectrum<float>(c->mps, bond, dev_out, ld, dev_rank, c->st);
+  }
+  return check_launch(c);
+}
+
+stn_status stn_set_layer_env(stn_ctx *c, int max_bond) {
+  if (!c || max_bond < 0 || max_bond > c->mps.ebond_alloc) return STN_EINVAL;
+  c->mps.ebond = max_bond;
+  return STN_OK;
+}
+
+stn_status stn_set_layer_lds(stn_ctx *c, int order) {
+  if (!c || (order != 0 && order != 32 && order != 64)) return STN_EINVAL;
+  c->mps.lds_order = order;
   return STN_OK;
 }
 

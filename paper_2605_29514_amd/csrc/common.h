@@ -45,11 +45,23 @@ __host__ __device__ inline cplx<D> cvt(cplx<S> a) { return {(D)a.x, (D)a.y}; }
 // Launch classes for timing and algorithmic work accounting.
 enum { K_TABLEAU = 0, K_BUILD, K_QR, K_GEMM, K_GRAM, K_EIGEN, K_SELECT, K_EXPECT, K_LAYER, K_COUNT };
 // Device work counters: [K_COUNT][2] flops/bytes, Jacobi sweeps, layer FP64
-// flops, then the fused kernel's per-phase cycle totals.
-constexpr int kPhaseBase = 2 * K_COUNT + 2, kPhases = 8, kWorkWords = kPhaseBase + kPhases;
+// flops, the fused kernel's per-phase cycle totals, then its branch counters
+// (kPath* below).
+constexpr int kPhaseBase = 2 * K_COUNT + 2, kPhases = 8, kPathBase = kPhaseBase + kPhases, kPaths = 8;
+constexpr int kWorkWords = kPathBase + kPaths;
+// Branch counters of the fused kernel (steps that took each route; the
+// largest eigen-solve order as an integer; cycles spent in the pivoted
+// Cholesky part of the FP32-path eigen-solve).
+enum { kPathEnv = 0, kPathQr, kPathEigLds, kPathEigGlobal, kPathEigGlobal129, kPathMaxOrder, kPathCholCycles,
+       kPathJacGlobal };
 // Largest doubled bond for which the fused kernel keeps the left-environment
-// Grams of a span (64 x 64 FP64 complex each) instead of a QR sweep.
-constexpr int kEnvBond = 64;
+// Grams of a span (FP64 complex) instead of a QR sweep; the Grams of a span
+// are packed into a per-shot store of n x kEnvStore^2 elements (smaller when
+// the stores of all shots would pass kEnvBudget bytes), and a span whose
+// Grams do not fit takes the QR sweep.
+constexpr int kEnvBond = 256;
+constexpr int kEnvStore = 128;
+constexpr size_t kEnvBudget = (size_t)24 << 30;
 
 // Host-side recorder: when active, launches of the selected classes are
 // bracketed by HIP events on their stream.
@@ -132,6 +144,8 @@ struct MpsDev {
   c64 *Es;   int64_t Es_cap;    // fused kernel: left-environment Grams of a span (FP64)
   c64 *Fs;   int64_t Fs_cap;    //               and their product scratch
   int ebond;                    // largest workspace bond the environment path accepts
+  int ebond_alloc;              // ... as allocated (ebond may be set lower)
+  int lds_order;                // fused kernel, FP32 path: eigen-solve order held in LDS (0: by chi)
   double *logp, *fid, *p0, *nrm;  // [S]
   double *pm;                   // [S] probability of the last recorded outcome
   int *trunc;                   // [S] set when chi_max dropped weight above the cut
@@ -198,6 +212,7 @@ template <typename T> void mps_move_right(const MpsDev &m, int c, hipStream_t st
 template <typename T> void mps_move_left(const MpsDev &m, int c, hipStream_t st);
 template <typename T> void mps_normalize_site(const MpsDev &m, int site, hipStream_t st);
 template <typename T> void mps_expect(const MpsDev &m, int l, int r, const c64 *d_ops, hipStream_t st);
+template <typename T> void mps_spectrum(const MpsDev &m, int b, double *d_out, int ld, int *d_rank, hipStream_t st);
 
 // ops builders (device): from the Pauli bits of P' (W words each, x then z)
 void launch_ops_rotation(const uint64_t *d_bits, int W, int l, int r, c64 *d_ops, hipStream_t st);

@@ -60,7 +60,8 @@ constexpr size_t eig_region(bool fp64, int en) {
 //   [vt_off, +kVtBytes): V^T (nn x k), or before it the F = E X of the
 //     step's Gram when that fits
 //   [x_off, +kXBytes): the centre block X of the right-to-left sweep, kept
-//     from step to step
+//     from step to step (sized so that four 256-thread blocks fit a compute
+//     unit)
 // The environment sweep, before X exists, uses the last two as one buffer
 // for its F = E B (kFElems FP64).  The GEMM staging overlaps only the first
 // bytes of V^T.  At 128 threads per shot four blocks still fit a compute
@@ -68,7 +69,7 @@ constexpr size_t eig_region(bool fp64, int en) {
 constexpr int kLdsStepN = 32;
 constexpr size_t kStepFactor = (size_t)kLdsStepN * (kLdsStepN + 1) * sizeof(c64);
 constexpr size_t kVtBytes = (size_t)kLdsStepN * kLdsStepN * sizeof(cplx<float>);
-constexpr size_t kXBytes = 8192;
+constexpr size_t kXBytes = 5120;
 constexpr int kXElems = kXBytes / sizeof(cplx<float>);
 constexpr int kFElems = (kVtBytes + kXBytes) / sizeof(c64);
 constexpr size_t vt_off(int nt) { return u_off(nt) + kStepFactor; }
@@ -78,6 +79,17 @@ constexpr size_t lds_bytes(int nt, bool fp64, int en) {
   return u_off(nt) + cmax(cmax(kUfix, eig_region(fp64, en)), fp64 ? 0 : kStepFactor + kVtBytes + kXBytes);
 }
 static_assert(lds_bytes(128, false, 32) * 4 <= 160 * 1024, "four 128-thread blocks per compute unit");
+// four 256-thread blocks as well, with room for the kernels' static LDS
+static_assert((lds_bytes(256, false, 32) + 1024) * 4 <= 160 * 1024, "four 256-thread blocks per compute unit");
+// FP32 path, truncation steps whose rho stays in global scratch: the largest
+// rank whose Gram K = Rs Rs^H (padded rows) fits the overlaid region
+constexpr int k_gram_order(int en) {
+  const size_t region = lds_bytes(64, false, en) - u_off(64);
+  int r = 0;
+  while ((size_t)(r + 1) * (r + 2) * sizeof(c64) <= region && r + 1 <= kEigIdx) ++r;
+  return r;
+}
+static_assert(k_gram_order(32) >= 40 && k_gram_order(64) == 64, "Gram orders held in LDS");
 // FP32 path: factors up to order 64 in LDS when chi_max is 17..32 (every
 // doubled bond then fits, at ~70 KB per block); otherwise up to 32 (~22 KB)
 // and larger orders in the shot's global scratch.
@@ -275,11 +287,20 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
   // E_j = sum_s B_j^s^H E_{j-1} B_j^s (FP64) instead of a QR sweep, and the
   // truncation uses rho = X^H E X, the same reduced density that X^H X gives
   // after orthonormalisation.  Otherwise: Householder QR.
+  // (The Grams are packed one after another in the shot's store: E_j, of
+  // order Dr_j, starts after E_l .. E_{j-1}; the path needs every doubled
+  // bond within the product scratch and the Grams within the store.)
   bool env = m.ebond > 0;
-  for (int j = l; j <= r && env; ++j) {
-    const int Dl = (j == l) ? b[j] : 2 * b[j], Dr = (j == r) ? b[j + 1] : 2 * b[j + 1];
-    env = Dl <= m.ebond && Dr <= m.ebond;
+  {
+    size_t need = 0;
+    for (int j = l; j <= r && env; ++j) {
+      const int Dl = (j == l) ? b[j] : 2 * b[j], Dr = (j == r) ? b[j + 1] : 2 * b[j + 1];
+      env = Dl <= m.ebond && Dr <= m.ebond;
+      if (j < r) need += (size_t)Dr * Dr;
+    }
+    env = env && need <= (size_t)m.Es_cap;
   }
+  if (m.prof && tid == 0) atomicAdd(&m.work[kPathBase + (env ? kPathEnv : kPathQr)], 1.0);
   // bond-2 blocks over [l, r]
   for (int j = l; j <= r; ++j) {
     const int dl = b[j], dr = b[j + 1];
@@ -330,7 +351,15 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
   __syncthreads();
   clk.lap(m, 2);
   c64 *Es = m.Es + (size_t)s * m.Es_cap, *Fs = m.Fs + (size_t)s * m.Fs_cap;
-  const int eb2 = m.ebond * m.ebond;
+  // offset of E_j (j in [l, r-1]) in the packed store: the orders of
+  // E_l .. E_{j-1} are the workspace bonds w[l+1] .. w[j] as the
+  // left-to-right sweep leaves them (the right-to-left sweep changes w[j]
+  // only after its last use of E_{j-1})
+  auto eoff = [&](int j) {
+    size_t o = 0;
+    for (int i = l + 1; i <= j; ++i) o += (size_t)w[i] * w[i];
+    return o;
+  };
   // the centre block X of the right-to-left sweep: the shot's T, or (FP32
   // path, a step small enough for the LDS buffers) the LDS X buffer
   cplx<T> *Xg = scr<T>(m.T, m.T_cap, s), *Xl = reinterpret_cast<cplx<T> *>(lds + x_off(NT));
@@ -350,7 +379,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     }
     for (int j = l + 1; j < r; ++j) {
       const int Dl = w[j], Dr = w[j + 1];
-      c64 *Ep = Es + (size_t)(j - 1 - l) * eb2, *Ej = Es + (size_t)(j - l) * eb2;
+      c64 *Ep = Es + eoff(j - 1), *Ej = Es + eoff(j);
       // FP32 path, small sites: F in LDS between two direct GEMMs
       const bool lf = sizeof(T) == 4 && Dl <= kDirectGemm / 2 && Dr <= kDirectGemm / 2 && Dl * 2 * Dr <= kFElems;
       c64 *F = lf ? reinterpret_cast<c64 *>(lds + vt_off(NT)) : Fs;
@@ -394,16 +423,21 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     const int Lx = w[j], nn = 2 * w[j + 1];
     cplx<T> *X = xl ? Xl : Xg;
     c64 *Gg = m.G + s * m.G_cap;
-    // FP32 path: when the factor fits the LDS order in use and the products
-    // are direct, rho goes straight into the LDS factor and the selection
-    // reads the eigenvectors there (lg); small steps also keep V^T and their
+    // FP32 path: when the step's order is at most 32 and the products are
+    // direct, rho goes straight into the LDS factor and the selection reads
+    // the eigenvectors there (lg); such steps also keep V^T and their
     // intermediates in LDS (ls).  Each global write read back after a barrier
     // costs a store and a load latency on the step's critical path.
-    const bool lg = sizeof(T) == 4 && nn <= eig_n && nn <= kDirectGemm && Lx <= kDirectGemm;
+    const bool lg = sizeof(T) == 4 && nn <= kLdsStepN && nn <= eig_n && Lx <= kDirectGemm;
     const bool ls = lg && nn <= kLdsStepN;
+    // FP32 path: the eigen-solve runs on rho in LDS (vectors read from its
+    // factor rows by the selection) when rho was formed there; any larger
+    // step reduces rho to the Gram of its Cholesky factor first (half the
+    // order at these ranks: measured faster than rho of order 33..64 in LDS)
+    const bool vl = sizeof(T) == 4 && lg;
     c64 *Gl = reinterpret_cast<c64 *>(lds + u_off(NT));
     if (env) {                                // rho = X^H (E_{j-1} X)
-      const c64 *Ep = Es + (size_t)(j - 1 - l) * eb2;
+      const c64 *Ep = Es + eoff(j - 1);
       c64 *F = ls && Lx * nn * sizeof(c64) <= kVtBytes ? reinterpret_cast<c64 *>(lds + vt_off(NT)) : Fs;
       blk_gemm<double, T, double, double, NT>(Lx, nn, Lx, Ep, Lx, 0, X, nn, 0, F, nn, lds);
       if (lg) {
@@ -424,6 +458,13 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     }
     clk.lap(m, 5);
     const c64 *Vsel = m.V + s * m.V_cap;     // sorted eigenvectors, nn x nn (not in LDS steps)
+    if (m.prof && tid == 0) {
+      const bool in_lds = sizeof(T) == 8 ? nn <= kJacLdsN : lg;
+      atomicAdd(&m.work[kPathBase + (in_lds ? kPathEigLds : nn <= 128 ? kPathEigGlobal : kPathEigGlobal129)], 1.0);
+      if (sizeof(T) == 8 && !in_lds) atomicAdd(&m.work[kPathBase + kPathJacGlobal], 1.0);
+      atomicMax(reinterpret_cast<unsigned long long *>(&m.work[kPathBase + kPathMaxOrder]), (unsigned long long)nn);
+    }
+    long long t_chol = 0;
     {
       const Fallback f = fallback(m, s);
       const bool li = nn <= kEigIdx;
@@ -452,29 +493,64 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         fe = 36.0 * nn * nn * (double)nn;
         Vsel = Gg;
       } else {
-        // FP32 path: pivoted Cholesky + one-sided Jacobi on the factor
+        // FP32 path: pivoted Cholesky + one-sided Jacobi on the factor, on
+        // one matrix in LDS: rho itself when it was formed there, else the
+        // Gram K = Rs Rs^H of
+        // the contiguous factor Rs (r x nn, in the shot's R scratch) that a
+        // left-looking pivoted Cholesky of rho in global scratch produces,
+        // when its rank fits; K has the nonzero eigenvalues of rho, and the
+        // eigenvectors of rho come back as Rs^H u / sqrt(lambda) (a
+        // product).  Past both, one-sided Jacobi on the rows of Rs in
+        // global scratch.  One eig_psd call site serves the LDS cases.
         const double ct = chol_tol(m.eps_cut, nn);
         double *ev = m.ev + s * m.ev_cap;
         c64 *V = m.V + s * m.V_cap;
         int *piv_l = reinterpret_cast<int *>(lds + kPiv), *pos_l = reinterpret_cast<int *>(lds + kPos);
-        double *dg_l = reinterpret_cast<double *>(lds + kDg);
-        if (lg) {
-          // eigenvalues to LDS, eigenvectors left in the factor rows
-          fe = eig_psd<NT>(nn, Gl, nn + 1, reinterpret_cast<double *>(lds + kEv), nullptr, m.err, piv_l, pos_l,
-                           dg_l, sweeps, ct, eig_conv_tol<T>(), eig_rot_tol<T>());
-        } else if (nn <= eig_n) {
-          // factor (rows padded by one) and index tables all in LDS: a call
-          // of its own, so that every access in it is a direct LDS access
-          const int ldw = nn + 1;
-          blk_each_rc<NT, 8, c64>(nn, nn, [&](int i, int j) { return Gg[i * nn + j]; },
-                                  [&](int i, int j, c64 v) { Gl[i * ldw + j] = v; });
-          __syncthreads();
-          fe = eig_psd<NT>(nn, Gl, ldw, ev, V, m.err, piv_l, pos_l, dg_l, sweeps, ct, eig_conv_tol<T>(),
-                           eig_rot_tol<T>());
+        double *dg_l = reinterpret_cast<double *>(lds + kDg), *evl = reinterpret_cast<double *>(lds + kEv);
+        c64 *Rs = reinterpret_cast<c64 *>(scr<T>(m.R, m.R_cap, s));
+        int eo = -1, rk = 0;
+        fe = 0;
+        if (vl) {
+          eo = nn;
         } else {
-          int *piv = li ? piv_l : f.piv;
-          double *dg = li ? dg_l : f.dg;
-          fe = eig_psd<NT>(nn, Gg, nn, ev, V, m.err, piv, pos, dg, sweeps, ct, eig_conv_tol<T>(), eig_rot_tol<T>());
+          double tr;
+          rk = chol_rows<NT>(nn, Gg, nn, Rs, nn, ct, f.dg, f.pos, reinterpret_cast<c64 *>(lds + kWp), m.err, &tr,
+                             &fe);
+          if (clk.on && tid == 0) t_chol = clock64();
+          if (rk >= 1 && rk <= (eig_n > 32 ? k_gram_order(64) : k_gram_order(32))) {
+            gemm_direct<double, double, double, double, NT>(rk, rk, nn, Rs, nn, 0, Rs, nn, 1, Gl, rk + 1);
+            __syncthreads();
+            fe += gemm_flops(rk, rk, nn);
+            eo = rk;
+          }
+        }
+        if (eo >= 0) {
+          fe += eig_psd<NT>(eo, Gl, eo + 1, evl, nullptr, m.err, piv_l, pos_l, dg_l, sweeps, ct, eig_conv_tol<T>(),
+                            eig_rot_tol<T>(), (vl && clk.on) ? &t_chol : nullptr);
+          if (!vl) {
+            // eigenvectors of K with nonzero eigenvalue, scaled:
+            // U[a][c] = u_c[a] / sqrt(lambda_c), u_c = conj(factor row pos[c]) / |row|
+            int r2 = 0;
+            for (int c = 0; c < rk; ++c) r2 += evl[c] > 0;
+            c64 *U = Gg;
+            blk_each_rc<NT, 4, c64>(
+                rk, r2, [&](int a, int c) { return Gl[(size_t)piv_l[pos_l[c]] * (rk + 1) + a]; },
+                [&](int a, int c, c64 v) { U[(size_t)a * r2 + c] = (dg_l[pos_l[c]] / sqrt(evl[c])) * cj(v); });
+            for (int c = tid; c < nn; c += NT) ev[c] = c < r2 ? evl[c] : 0.0;
+            __syncthreads();
+            if (r2 > 0) {
+              gemm_direct<double, double, double, double, NT>(nn, r2, rk, Rs, nn, 1, U, r2, 0, V, nn);
+              fe += gemm_flops(nn, r2, rk);
+            } else {
+              for (int i = tid; i < nn; i += NT) V[(size_t)i * nn] = mk<double>(i == 0 ? 1.0 : 0.0, 0);
+            }
+            __syncthreads();
+          }
+        } else {
+          for (int q = tid; q < rk; q += NT) f.piv[q] = q;
+          __syncthreads();
+          fe += jac_rows<NT>(nn, rk, Rs, nn, ev, V, m.err, f.piv, f.pos, f.dg, sweeps, eig_conv_tol<T>(),
+                             eig_rot_tol<T>());
         }
       }
       if (tid == 0) {
@@ -482,12 +558,13 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         add_work(m, cls, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
         if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
         if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)*sweeps);
+        if (clk.on && t_chol) atomicAdd(&m.work[kPathBase + kPathCholCycles], (double)(t_chol - clk.t));
       }
       clk.lap(m, 6);
     }
     int k;
     cplx<T> *Vt = ls ? reinterpret_cast<cplx<T> *>(lds + vt_off(NT)) : scr<T>(m.Vt, m.Vt_cap, s);
-    if (lg) {
+    if (vl) {
       const double *evl = reinterpret_cast<const double *>(lds + kEv);
       const int *rk = reinterpret_cast<const int *>(lds + kPos), *pv = reinterpret_cast<const int *>(lds + kPiv);
       const double *rn = reinterpret_cast<const double *>(lds + kDg);
@@ -643,7 +720,7 @@ __global__ void k_clear_words(uint64_t *a, uint64_t *b, int n) {
 template <typename T, int NT>
 void launch_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
                   const double *d_theta, int64_t stride, const RotLayer &L, hipStream_t st) {
-  const int en = eig_lds_order(m.chi);
+  const int en = m.lds_order ? m.lds_order : eig_lds_order(m.chi);
   if (m.prof)
     KLAUNCH(K_LAYER, (k_layer<T, NT, true>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_pbits,
             d_psgn, W, SW, d_theta, stride, L, en);
@@ -664,7 +741,7 @@ template <typename T, int NT>
 void launch_meas(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *d_ops, const c64 *d_eops,
                  const MeasStep &a, const double *d_u, const uint8_t *d_forced, uint8_t *d_out, double *d_prob,
                  uint64_t *d_negmask, uint64_t *d_mmask, hipStream_t st) {
-  const int en = eig_lds_order(m.chi);
+  const int en = m.lds_order ? m.lds_order : eig_lds_order(m.chi);
   if (m.prof)
     KLAUNCH(K_EXPECT, (k_meas<T, NT, true>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_snap_sign,
             d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, en);

@@ -366,9 +366,19 @@ __device__ void reflect_cols(int m, int nc, int k, int j0, int j1, cplx<T> *A, c
       c64 wt = mk<double>(0, 0);
       for (int gg = 0; gg < G; ++gg) wt = wt + wp[gg * CL + jj];
       wt = 2.0 * wt;
-      for (int i = k + g; i < m; i += G) {
-        c64 a = cvt<double>(A[(size_t)i * nc + j]) - vs[i] * wt;
-        A[(size_t)i * nc + j] = cvt<T>(a);
+      // four rows per group: their loads are issued before the first store
+      // (a load after a store to memory the compiler cannot prove distinct
+      // would otherwise wait for the previous element's round trip)
+      for (int i0 = k + g; i0 < m; i0 += 4 * G) {
+        cplx<T> av[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u * G < m) av[u] = A[(size_t)(i0 + u * G) * nc + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * G;
+          if (i < m) A[(size_t)i * nc + j] = cvt<T>(cvt<double>(av[u]) - vs[i] * wt);
+        }
       }
     }
     __syncthreads();
@@ -741,76 +751,16 @@ constexpr int kEigTpp = 8;        // threads per row pair (the width of sum8)
 constexpr int kEigRegN = 32;      // rows up to this length are held in registers per round
 constexpr int kEigMaxSweeps = 40;
 
+// Steps 2 and 3 of eig_psd on r factor rows of length nn (rows piv[0..r)
+// of G, leading dimension ld): one-sided Jacobi, then eigenvalues into ev
+// (descending, 0 from r to nn) and eigenvectors into Vout or left in the
+// rows (see eig_psd).  Scratch: pos (nn ints), dg (nn doubles).  Returns the
+// flops executed.
 template <int NT>
-__device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *err, int *piv, int *pos,
-                          double *dg, int *sweeps_out, double chol_tol, double conv_tol, double rot_tol) {
+__device__ double jac_rows(int nn, int r, c64 *G, int ld, double *ev, c64 *Vout, int *err, const int *piv,
+                           int *pos, double *dg, int *sweeps_out, double conv_tol, double rot_tol) {
   const int tid = threadIdx.x;
-  constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
-  __shared__ double amv[2 * NW];
-  __shared__ int ami[2 * NW];
-  double trp = 0;
-  for (int i = tid; i < nn; i += NT) {
-    const double d = G[(size_t)i * ld + i].x;
-    dg[i] = d;
-    trp += d;
-  }
-  const double tr = bsum<NT>(trp);
-  if (tid == 0 && (!(tr == tr) || isinf(tr))) atomicOr(err, STN_ERR_NUMERIC);
-  const double thr = chol_tol * tr;
   double flops = 0;
-  // 1. pivoted Cholesky.  The Schur updates use the raw pivot row S_p scaled
-  // by 1/d (no separate pass to publish the normalised row, so one barrier
-  // per pivot, inside bargmax); pos[j] = the step that pivoted j (nn: not
-  // yet).  The rows are normalised, and zeroed at the columns pivoted
-  // before them, in one pass after the loop.
-  int r = 0;
-  {
-    double v = -INFINITY;
-    int vi = 0x7fffffff;
-    for (int i = tid; i < nn; i += NT) {
-      pos[i] = nn;
-      if (dg[i] > v) { v = dg[i]; vi = i; }
-    }
-    double d;
-    int p;
-    bargmax<NT>(v, vi, d, p, amv, ami, 0);
-    const int di = NT / nn, dj = NT - (NT / nn) * nn;
-    for (int k = 0; k < nn; ++k) {
-      if (!(d > thr) || !(tr > 0)) break;
-      const double id = 1.0 / d;
-      if (tid == 0) { piv[k] = p; pos[p] = k; }
-      const c64 *R = G + (size_t)p * ld;
-      int i = tid / nn, j = tid - (tid / nn) * nn;
-      for (int e = tid; e < nn * nn; e += NT, i += di, j += dj) {
-        if (j >= nn) { j -= nn; ++i; }
-        if (i == p || j == p || i == j || pos[i] < nn || pos[j] < nn) continue;
-        G[(size_t)i * ld + j] = G[(size_t)i * ld + j] - id * (cj(R[i]) * R[j]);
-      }
-      v = -INFINITY;
-      vi = 0x7fffffff;
-      for (int q = tid; q < nn; q += NT) {
-        if (q == p || pos[q] < nn) continue;
-        const double nd = dg[q] - id * norm2(R[q]);
-        dg[q] = nd;
-        if (nd > v) { v = nd; vi = q; }
-      }
-      flops += 8.0 * (double)(nn - k - 1) * (nn - k - 1);
-      r = k + 1;
-      bargmax<NT>(v, vi, d, p, amv, ami, (k + 1) & 1);
-    }
-    // row k of R: sqrt(d_k) at its pivot, 0 at columns pivoted before step
-    // k, S_pk / sqrt(d_k) elsewhere (dg[p_k] still holds d_k)
-    for (int e = tid; e < r * nn; e += NT) {
-      const int kk = e / nn, jj = e - kk * nn;
-      const int pk = piv[kk];
-      const double dk = dg[pk];
-      c64 *row = G + (size_t)pk * ld;
-      if (jj == pk) row[jj] = mk<double>(sqrt(dk), 0);
-      else if (pos[jj] < kk) row[jj] = mk<double>(0, 0);
-      else row[jj] = (1.0 / sqrt(dk)) * row[jj];
-    }
-    __syncthreads();
-  }
   // 2. one-sided Jacobi on the rows piv[0..r)
   int sweeps = 0;
   if (r >= 2) {
@@ -953,6 +903,178 @@ __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *er
   if (sweeps_out && tid == 0) *sweeps_out = sweeps;
   __syncthreads();
   return flops;
+}
+
+// Pivoted Cholesky of a Hermitian positive semi-definite nn x nn matrix A
+// (leading dimension lda, read only), left-looking: step k takes the largest
+// remaining diagonal d of the Schur complement as pivot p (ties to the lower
+// index) and forms only the new factor row
+//   R_k[j] = (A[p][j] - sum_{t<k} conj(R_t[p]) R_t[j]) / sqrt(d)
+// (sqrt(d) at j = p, 0 at the columns pivoted before), so no trailing matrix
+// is written back: a step reads the rows made so far, all its loads in
+// flight together.  The rows go to R (leading dimension ldr), contiguous in
+// pivot order, with R^H R = A up to the part left out; the Schur diagonal
+// follows each row (d_q -= |R_k[q]|^2).  Stops once d <= chol_tol tr A (the
+// eigenvalues left out are then at most nn chol_tol tr A in total), returns
+// the rank r and (to every thread) tr A in *trace.
+// Scratch: dg (nn doubles), pos (nn ints), wp (NT complex doubles).
+template <int NT>
+__device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double chol_tol, double *dg, int *pos,
+                         c64 *wp, int *err, double *trace, double *flops) {
+  const int tid = threadIdx.x;
+  constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
+  __shared__ double amv[2 * NW];
+  __shared__ int ami[2 * NW];
+  double trp = 0, v = -INFINITY;
+  int vi = 0x7fffffff;
+  for (int i = tid; i < nn; i += NT) {
+    const double d = A[(size_t)i * lda + i].x;
+    dg[i] = d;
+    pos[i] = nn;
+    trp += d;
+    if (d > v) { v = d; vi = i; }
+  }
+  const double tr = bsum<NT>(trp);
+  *trace = tr;
+  if (tid == 0 && (!(tr == tr) || isinf(tr))) atomicOr(err, STN_ERR_NUMERIC);
+  const double thr = chol_tol * tr;
+  double d;
+  int p;
+  bargmax<NT>(v, vi, d, p, amv, ami, 0);
+  int CL, G;
+  col_split<NT>(nn, CL, G);
+  const int jj = tid % CL, g = tid / CL;
+  int r = 0;
+  double fl = 0;
+  for (int k = 0; k < nn; ++k) {
+    if (!(d > thr) || !(tr > 0)) break;
+    const double isd = 1.0 / sqrt(d);
+    for (int jb = 0; jb < nn; jb += CL) {
+      const int j = jb + jj;
+      const bool live = j < nn && j != p && pos[j] >= nn;
+      c64 acc = mk<double>(0, 0);
+      if (live) {
+        // the group's rows t = g, g + G, ...: four at a time, loads first
+        for (int t0 = g; t0 < k; t0 += 4 * G) {
+          c64 rp[4], rj[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * G;
+            if (t < k) { rp[u] = R[(size_t)t * ldr + p]; rj[u] = R[(size_t)t * ldr + j]; }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (t0 + u * G < k) acc = acc + cj(rp[u]) * rj[u];
+        }
+      }
+      if (G > 1) {
+        wp[tid] = acc;
+        __syncthreads();
+        if (g == 0)
+          for (int gg = 1; gg < G; ++gg) acc = acc + wp[gg * CL + jj];
+      }
+      if (g == 0 && j < nn) {
+        c64 val;
+        if (j == p) val = mk<double>(sqrt(d), 0);
+        else if (!live) val = mk<double>(0, 0);
+        else val = isd * (A[(size_t)p * lda + j] - acc);
+        R[(size_t)k * ldr + j] = val;
+      }
+      if (G > 1) __syncthreads();
+    }
+    __syncthreads();
+    fl += 8.0 * (double)k * (nn - k);
+    // Schur diagonal and the next pivot
+    v = -INFINITY;
+    vi = 0x7fffffff;
+    for (int q = tid; q < nn; q += NT) {
+      if (q == p || pos[q] < nn) continue;
+      const double nd = dg[q] - norm2(R[(size_t)k * ldr + q]);
+      dg[q] = nd;
+      if (nd > v) { v = nd; vi = q; }
+    }
+    __syncthreads();
+    if (tid == 0) pos[p] = k;
+    r = k + 1;
+    bargmax<NT>(v, vi, d, p, amv, ami, (k + 1) & 1);
+  }
+  *flops += fl;
+  return r;
+}
+
+template <int NT>
+__device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *err, int *piv, int *pos,
+                          double *dg, int *sweeps_out, double chol_tol, double conv_tol, double rot_tol,
+                          long long *t_chol = nullptr) {
+  const int tid = threadIdx.x;
+  constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
+  __shared__ double amv[2 * NW];
+  __shared__ int ami[2 * NW];
+  double trp = 0;
+  for (int i = tid; i < nn; i += NT) {
+    const double d = G[(size_t)i * ld + i].x;
+    dg[i] = d;
+    trp += d;
+  }
+  const double tr = bsum<NT>(trp);
+  if (tid == 0 && (!(tr == tr) || isinf(tr))) atomicOr(err, STN_ERR_NUMERIC);
+  const double thr = chol_tol * tr;
+  double flops = 0;
+  // 1. pivoted Cholesky.  The Schur updates use the raw pivot row S_p scaled
+  // by 1/d (no separate pass to publish the normalised row, so one barrier
+  // per pivot, inside bargmax); pos[j] = the step that pivoted j (nn: not
+  // yet).  The rows are normalised, and zeroed at the columns pivoted
+  // before them, in one pass after the loop.
+  int r = 0;
+  {
+    double v = -INFINITY;
+    int vi = 0x7fffffff;
+    for (int i = tid; i < nn; i += NT) {
+      pos[i] = nn;
+      if (dg[i] > v) { v = dg[i]; vi = i; }
+    }
+    double d;
+    int p;
+    bargmax<NT>(v, vi, d, p, amv, ami, 0);
+    const int di = NT / nn, dj = NT - (NT / nn) * nn;
+    for (int k = 0; k < nn; ++k) {
+      if (!(d > thr) || !(tr > 0)) break;
+      const double id = 1.0 / d;
+      if (tid == 0) { piv[k] = p; pos[p] = k; }
+      const c64 *R = G + (size_t)p * ld;
+      int i = tid / nn, j = tid - (tid / nn) * nn;
+      for (int e = tid; e < nn * nn; e += NT, i += di, j += dj) {
+        if (j >= nn) { j -= nn; ++i; }
+        if (i == p || j == p || i == j || pos[i] < nn || pos[j] < nn) continue;
+        G[(size_t)i * ld + j] = G[(size_t)i * ld + j] - id * (cj(R[i]) * R[j]);
+      }
+      v = -INFINITY;
+      vi = 0x7fffffff;
+      for (int q = tid; q < nn; q += NT) {
+        if (q == p || pos[q] < nn) continue;
+        const double nd = dg[q] - id * norm2(R[q]);
+        dg[q] = nd;
+        if (nd > v) { v = nd; vi = q; }
+      }
+      flops += 8.0 * (double)(nn - k - 1) * (nn - k - 1);
+      r = k + 1;
+      bargmax<NT>(v, vi, d, p, amv, ami, (k + 1) & 1);
+    }
+    // row k of R: sqrt(d_k) at its pivot, 0 at columns pivoted before step
+    // k, S_pk / sqrt(d_k) elsewhere (dg[p_k] still holds d_k)
+    for (int e = tid; e < r * nn; e += NT) {
+      const int kk = e / nn, jj = e - kk * nn;
+      const int pk = piv[kk];
+      const double dk = dg[pk];
+      c64 *row = G + (size_t)pk * ld;
+      if (jj == pk) row[jj] = mk<double>(sqrt(dk), 0);
+      else if (pos[jj] < kk) row[jj] = mk<double>(0, 0);
+      else row[jj] = (1.0 / sqrt(dk)) * row[jj];
+    }
+    __syncthreads();
+  }
+  if (t_chol && tid == 0) *t_chol = clock64();
+  return flops + jac_rows<NT>(nn, r, G, ld, ev, Vout, err, piv, pos, dg, sweeps_out, conv_tol, rot_tol);
 }
 
 // Tolerances of the one-sided Jacobi, which serves the FP32 path.  Its

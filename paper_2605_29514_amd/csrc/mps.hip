@@ -29,7 +29,7 @@ using namespace stnk;
 constexpr int TB = 256;          // threads per block of the per-step kernels
 constexpr int kEigLdsN = 64;     // FP32 path: factor in LDS up to this order (66.5 KB)
 constexpr int kJacLdsN = 32;     // FP64 path: Jacobi G and V in LDS up to this order (2 x 16.5 KB)
-constexpr int kEigIdx = 1040;    // eigen-solve index / pair tables (orders up to 2 x 512 + 16)
+constexpr int kEigIdx = 2064;    // eigen-solve index / pair tables (orders up to 2 x 1024 + 16)
 constexpr size_t kQrLdsMat = 16 * 1024;
 
 __device__ inline bool first_block() { return blockIdx.x == 0 && threadIdx.x == 0; }
@@ -237,6 +237,41 @@ __global__ void k_eig(MpsDev m, int j) {
   // work: the method's operation count; bytes: read G, write eigenvalues and vectors
   if (threadIdx.x == 0) add_work(m, K_EIGEN, fe, 16.0 * 2 * nn * nn + 8.0 * nn);
   if (threadIdx.x == 0 && m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)sweeps);
+}
+
+// Squared Schmidt values across bond b (between sites b-1 and b) with the
+// orthogonality centre at site b: sites left of b are left-orthonormal and
+// right of b right-orthonormal, so the singular values of the centre tensor
+// as a dl x 2 dr matrix X are the Schmidt values (Eq. 8's lambda_i).  FP64
+// Gram X X^H, two-sided Jacobi (relative accuracy), eigenvalues descending,
+// normalised to sum 1; out[s][i] for i < ld (0 past the bond), rank[s] = dl.
+template <typename T>
+__global__ void k_spectrum(MpsDev m, int b, double *out, int ld, int *rank) {
+  extern __shared__ __align__(16) char lds[];
+  const int s = blockIdx.x;
+  const int dl = bnd(m, s)[b], dr = bnd(m, s)[b + 1];
+  const cplx<T> *A = slot<T>(m, b, s);
+  c64 *Gg = m.G + s * m.G_cap;
+  gemm_direct<T, T, double, double, TB>(dl, dl, 2 * dr, A, 2 * dr, 0, A, 2 * dr, 1, Gg, dl);
+  __syncthreads();
+  int *pos = reinterpret_cast<int *>(lds);
+  int *pp = pos + kEigIdx, *pq = pp + kEigIdx / 2;
+  double *pc = reinterpret_cast<double *>(pq + kEigIdx / 2);
+  double *ps = pc + kEigIdx / 2;
+  c64 *pe = reinterpret_cast<c64 *>(ps + kEigIdx / 2);
+  __shared__ int sweeps;
+  double *ev = m.ev + s * m.ev_cap;
+  jacobi_block<TB>(dl, Gg, dl, m.V + s * m.V_cap, ev, m.E + s * m.E_cap, m.err, pos, pc, ps, pe, pp, pq, &sweeps,
+                   1e-18, 1e-15);
+  double part = 0;
+  for (int i = threadIdx.x; i < dl; i += TB) part += fmax(ev[i], 0.0);
+  const double tot = bsum<TB>(part);
+  for (int i = threadIdx.x; i < ld; i += TB)
+    out[(size_t)s * ld + i] = (i < dl && tot > 0) ? fmax(ev[i], 0.0) / tot : 0.0;
+  if (threadIdx.x == 0) {
+    if (rank) rank[s] = dl;
+    add_work(m, K_EXPECT, gemm_flops(dl, dl, 2 * dr) + 36.0 * dl * dl * (double)dl, 16.0 * (2.0 * dl * dr + dl * dl));
+  }
 }
 
 template <typename T>
@@ -658,11 +693,17 @@ void launch_outcome(const MpsDev &m, const uint64_t *d_snap_sign, int pivot, int
                      d_u, d_forced, n_meas, mi, d_out, d_prob, d_negmask, d_mmask);
 }
 
+template <typename T> void mps_spectrum(const MpsDev &m, int b, double *d_out, int ld, int *d_rank, hipStream_t st) {
+  KLAUNCH(K_EXPECT, k_spectrum<T>, dim3(m.S), dim3(TB), eig_lds(), st, m, b, d_out, ld, d_rank);
+}
+
 // Raise the dynamic-LDS limit of the kernels that stage matrices in LDS
 // (gfx950 has 160 KB per CU).  Returns the first HIP error, if any.
 template <typename T> hipError_t mps_prepare(int max_rows) {
   hipError_t e = hipFuncSetAttribute((const void *)k_eig<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)eig_lds());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_spectrum<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_lds());
   const int q = (int)qr_lds(max_rows);
   for (const void *f : {(const void *)k_qr_lr<T>, (const void *)k_qr_move_r<T>, (const void *)k_qr_move_l<T>}) {
     hipError_t e2 = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, q);
@@ -681,6 +722,7 @@ template <typename T> hipError_t mps_prepare(int max_rows) {
   template void mps_move_right<T>(const MpsDev &, int, hipStream_t);                  \
   template void mps_move_left<T>(const MpsDev &, int, hipStream_t);                   \
   template void mps_normalize_site<T>(const MpsDev &, int, hipStream_t);              \
-  template void mps_expect<T>(const MpsDev &, int, int, const c64 *, hipStream_t);
+  template void mps_expect<T>(const MpsDev &, int, int, const c64 *, hipStream_t);           \
+  template void mps_spectrum<T>(const MpsDev &, int, double *, int, int *, hipStream_t);
 INST(float)
 INST(double)

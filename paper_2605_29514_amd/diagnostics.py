@@ -1,10 +1,9 @@
 """Truncation diagnostics of a run: what chi_max does to the state and to the
 syndromes (Sec. IV.B, Figs. 2-3), from the MPS and the records only.
 
-* schmidt_values: squared Schmidt values across one cut of one shot's state,
-  from the site tensors the library hands back (any gauge: QR from the left,
-  LQ from the right, SVD of the bond matrix between them).  Host-side
-  analysis of a returned state, not part of the simulation.
+* the Schmidt spectrum across a cut comes from the library (stn_spectrum:
+  FP64 Gram of the centre tensor and Jacobi eigen-solve on the device, every
+  shot at once); nothing here recomputes it from returned tensors.
 * detection_rates: per syndrome round, the fraction of detection events
   (an ancilla outcome that differs from the same ancilla's previous one; in
   the first round only the Z checks, whose noiseless outcome is 0).
@@ -22,29 +21,6 @@ import json
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
-
-
-def schmidt_values(tensors: Sequence[np.ndarray], cut: int) -> np.ndarray:
-    """Squared Schmidt values, descending and normalised to sum 1, of the
-    state given by site tensors A_j of shape (dl, 2, dr), across the bond
-    between sites cut and cut + 1."""
-    n = len(tensors)
-    if not 0 <= cut < n - 1:
-        raise ValueError(f"cut {cut} outside 0..{n - 2}")
-    R = np.ones((1, 1), complex)
-    for j in range(cut + 1):
-        t = np.tensordot(R, np.asarray(tensors[j], complex), axes=([1], [0]))
-        a, _, dr = t.shape
-        _, R = np.linalg.qr(t.reshape(a * 2, dr))
-    L = np.ones((1, 1), complex)
-    for j in range(n - 1, cut, -1):
-        t = np.tensordot(np.asarray(tensors[j], complex), L, axes=([2], [0]))
-        dl = t.shape[0]
-        _, r = np.linalg.qr(t.reshape(dl, -1).conj().T)
-        L = r.conj().T
-    w = np.linalg.svd(R @ L, compute_uv=False) ** 2
-    tot = w.sum()
-    return np.sort(w / tot)[::-1] if tot > 0 else w
 
 
 def measurement_rounds(circ) -> List[np.ndarray]:
@@ -74,7 +50,10 @@ def detection_rates(circ, records: np.ndarray) -> List[float]:
 def chi_sweep(circ, chis: Sequence[int], precision: str = "fp32", shot: int = 0,
               cut: Optional[int] = None, device: str = "cuda:0", layer_mode: int = 0,
               top: int = 64) -> Dict[int, dict]:
-    """Runs circ at every chi_max in chis (same inputs, sampled records)."""
+    """Runs circ at every chi_max in chis (same inputs, sampled records);
+    `cut` names the bond between sites cut and cut + 1 (default: the centre),
+    and the spectra (the largest `top` squared Schmidt values of `shot`) come
+    from the device before every round's ancilla measurement."""
     from . import stn
     import torch
     cut = circ.n // 2 - 1 if cut is None else cut
@@ -87,7 +66,8 @@ def chi_sweep(circ, chis: Sequence[int], precision: str = "fp32", shot: int = 0,
             if op[0] == "measure" and op[2]:            # an ancilla round ends here
                 stn.run_prepared(sim, ops, start, i, records=res)
                 sim.sync()
-                spectra.append(schmidt_values(sim.mps(shot), cut)[:top].tolist())
+                vals, _ = sim.spectrum(cut + 1)
+                spectra.append(vals[shot, :top].cpu().numpy().tolist())
                 start = i
         stn.run_prepared(sim, ops, start, None, records=res)
         lp, te = sim.logprob()

@@ -45,7 +45,9 @@ EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn
            "stn_set_site", "stn_set_center", "stn_set_layer_mode", "stn_set_layer_threads", "stn_reset",
            "stn_tape_bytes", "stn_tape_begin", "stn_tape_end", "stn_adjoint_bytes", "stn_adjoint_init",
            "stn_adjoint_zero", "stn_backward", "stn_checkpoint_bytes", "stn_checkpoint_save",
-           "stn_checkpoint_load", "stn_profile_phases", "stn_adjoint_truncated"]
+           "stn_checkpoint_load", "stn_profile_phases", "stn_adjoint_truncated", "stn_profile_paths",
+           "stn_set_layer_lds", "stn_spectrum",
+           "stn_set_layer_env"]
 K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect", "layer"]
 
 
@@ -105,6 +107,10 @@ def load(path: str = LIB_PATH):
     lib.stn_tape_bytes.argtypes = [vp, i32]
     lib.stn_tape_begin.restype = i32
     lib.stn_tape_begin.argtypes = [vp, vp, ctypes.c_size_t, i32]
+    lib.stn_set_layer_env.restype = i32
+    lib.stn_set_layer_env.argtypes = [vp, i32]
+    lib.stn_spectrum.restype = i32
+    lib.stn_spectrum.argtypes = [vp, i32, vp, i32, vp]
     lib.stn_tape_end.restype = i32
     lib.stn_tape_end.argtypes = [vp, ctypes.POINTER(i32)]
     lib.stn_adjoint_bytes.restype = ctypes.c_size_t
@@ -119,6 +125,10 @@ def load(path: str = LIB_PATH):
     lib.stn_adjoint_truncated.argtypes = [vp, vp]
     lib.stn_profile_phases.restype = i32
     lib.stn_profile_phases.argtypes = [vp, vp]
+    lib.stn_set_layer_lds.restype = i32
+    lib.stn_set_layer_lds.argtypes = [vp, i32]
+    lib.stn_profile_paths.restype = i32
+    lib.stn_profile_paths.argtypes = [vp, vp]
     lib.stn_checkpoint_bytes.restype = ctypes.c_size_t
     lib.stn_checkpoint_bytes.argtypes = [vp]
     lib.stn_checkpoint_save.restype = i32
@@ -155,7 +165,7 @@ class Simulator:
 
     def __init__(self, n_qubits: int, n_shots: int, chi_max: int, precision: str = "fp32",
                  eps_cut: Optional[float] = None, device: str = "cuda:0", poison: bool = False,
-                 layer_mode: int = 0, layer_threads: int = 0, stream=None):
+                 layer_mode: int = 0, layer_threads: int = 0, stream=None, layer_lds: int = 0):
         """stream: torch.cuda.Stream every launch goes to (default: the
         current stream); a side stream is needed to capture HIP graphs."""
         import torch
@@ -189,6 +199,8 @@ class Simulator:
             self.set_layer_mode(layer_mode)
         if layer_threads:
             self.set_layer_threads(layer_threads)
+        if layer_lds:
+            self.set_layer_lds(layer_lds)
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -339,6 +351,18 @@ class Simulator:
             self.set_site(shot, j, t)
         self._check(self.lib.stn_set_center(self.ctx, center))
 
+    def spectrum(self, bond: int):
+        """Squared Schmidt values across the cut between sites bond-1 and bond
+        of every shot, computed on the device: (values [S, ld] descending,
+        normalised to sum 1, zero past the bond; bond dimensions [S])."""
+        t = self.torch
+        ld = max(1, min(self.chi, 1 << min(bond, self.n - bond, 30)))
+        out = t.empty((self.S, ld), dtype=t.float64, device=self.device)
+        rank = t.empty(self.S, dtype=t.int32, device=self.device)
+        self._check(self.lib.stn_spectrum(self.ctx, int(bond), ctypes.c_void_p(out.data_ptr()), ld,
+                                          ctypes.c_void_p(rank.data_ptr())))
+        return out, rank
+
     def center(self) -> int:
         return self.lib.stn_center(self.ctx)
 
@@ -375,9 +399,25 @@ class Simulator:
         names = ["angles_single", "moves", "build", "lr_qr", "lr_absorb", "gram", "eigen", "select_trunc"]
         return dict(zip(names, out.tolist()))
 
+    def profile_paths(self) -> dict:
+        """Fused-kernel branch counters (see stn_profile_paths)."""
+        out = np.zeros(8, np.float64)
+        self._check(self.lib.stn_profile_paths(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
+        names = ["env_steps", "qr_steps", "eig_lds", "eig_global", "eig_global_gt128", "max_order",
+                 "chol_cycles", "jacobi64_global"]
+        return dict(zip(names, out.tolist()))
+
     def set_layer_mode(self, mode: int):
         """0 automatic, 1 per-step kernels, 2 fused per-shot layer kernel."""
         self._check(self.lib.stn_set_layer_mode(self.ctx, int(mode)))
+
+    def set_layer_lds(self, order: int):
+        """Eigen-solve order kept in LDS by the fused kernel (0 auto, 32, 64)."""
+        self._check(self.lib.stn_set_layer_lds(self.ctx, int(order)))
+
+    def set_layer_env(self, max_bond: int):
+        """Largest doubled bond of the environment-Gram sweep (0: QR sweep only)."""
+        self._check(self.lib.stn_set_layer_env(self.ctx, int(max_bond)))
 
     def set_layer_threads(self, threads: int):
         """Threads per shot of the fused layer kernel (64, 128 or 256)."""
@@ -474,13 +514,13 @@ def load_inputs(dst_ops, src_ops):
 
 def run_circuit(circ, chi_max: int, precision: str = "fp32", eps_cut: Optional[float] = None,
                 device: str = "cuda:0", forced: Optional[np.ndarray] = None, sim: Optional[Simulator] = None,
-                layer_mode: int = 0, layer_threads: int = 0):
+                layer_mode: int = 0, layer_threads: int = 0, layer_lds: int = 0):
     """Simulates every shot of a workload Circuit on the GPU.  Returns a dict
     with records [S, M] uint8, prob [S, M], logp [S], trunc_err [S] (numpy)
     and the Simulator (for tableau / MPS inspection)."""
     if sim is None:
         sim = Simulator(circ.n, circ.n_shots, chi_max, precision, eps_cut, device, layer_mode=layer_mode,
-                        layer_threads=layer_threads)
+                        layer_threads=layer_threads, layer_lds=layer_lds)
     ops = prepare(circ, device, forced)
     res = run_prepared(sim, ops)
     lp, te = sim.logprob()
@@ -489,3 +529,59 @@ def run_circuit(circ, chi_max: int, precision: str = "fp32", eps_cut: Optional[f
     prob = torch.cat([r[1] for r in res], dim=1).cpu().numpy() if res else np.zeros((circ.n_shots, 0))
     return {"records": rec, "prob": prob, "logp": lp.cpu().numpy(), "trunc_err": te.cpu().numpy(),
             "sim": sim}
+
+
+def run_waves(circ, chi_max: int, wave: int, precision: str = "fp32", eps_cut: Optional[float] = None,
+              device: str = "cuda:0", stop_op: Optional[int] = None, layer_mode: int = 0,
+              layer_threads: int = 0, layer_lds: int = 0, use_graph: bool = True, log=None):
+    """Simulates the shots of a workload Circuit in waves of `wave` shots on
+    one context (the device memory of a context grows with its shot count:
+    at large chi_max the whole batch does not fit).  With use_graph, stn_reset
+    and the circuit's ops [0, stop_op) are captured once as a HIP graph on a
+    side stream and replayed for every wave with that wave's inputs loaded
+    into the captured buffers; otherwise each wave runs eagerly after
+    stn_reset.  The last wave is padded with copies of its last shot
+    (results dropped).  Returns records [S, M], prob [S, M], logp [S],
+    trunc_err [S] and max_bond [S] (numpy; M counts the measurements run)."""
+    import torch
+    S = circ.n_shots
+    wave = max(1, min(int(wave), S))
+    per_shot = any(o["op"] == "rotate" and not np.all(o["theta"] == o["theta"][:1]) for o in circ.ops)
+    stream = torch.cuda.Stream(device=device) if use_graph else None
+    sim = Simulator(circ.n, wave, chi_max, precision, eps_cut, device, layer_mode=layer_mode,
+                    layer_threads=layer_threads, layer_lds=layer_lds, stream=stream)
+    out = {"records": [], "prob": [], "logp": [], "trunc_err": [], "max_bond": []}
+    graph, gres, gops = None, None, None
+    for w0 in range(0, S, wave):
+        take = np.minimum(np.arange(w0, w0 + wave), S - 1)
+        cw = circ.shot_select(take)
+        ops = prepare(cw, device, per_shot_theta=per_shot)[:stop_op]
+        if use_graph:
+            if graph is None:
+                gops = ops
+                graph, gres = capture(sim, gops)
+            else:
+                load_inputs(gops, ops)
+            # the replay goes to the current stream: make that the library's
+            # stream, ordered after the input copies of load_inputs
+            sim.stream.wait_stream(torch.cuda.current_stream(sim.device))
+            with torch.cuda.stream(sim.stream):
+                graph.replay()
+            res = gres
+        else:
+            sim.reset()
+            res = run_prepared(sim, ops)
+        lp, te = sim.logprob()
+        torch.cuda.current_stream(sim.device).wait_stream(sim.stream)
+        keep = min(wave, S - w0)
+        if res:
+            out["records"].append(torch.cat([r[0] for r in res], dim=1)[:keep].cpu().numpy())
+            out["prob"].append(torch.cat([r[1] for r in res], dim=1)[:keep].cpu().numpy())
+        out["logp"].append(lp[:keep].cpu().numpy())
+        out["trunc_err"].append(te[:keep].cpu().numpy())
+        out["max_bond"].append(sim.bonds()[:keep].max(axis=1))
+        if log:
+            log(f"wave of shots {w0}..{w0 + keep - 1} done")
+    res = {k: (np.concatenate(v) if v else None) for k, v in out.items()}
+    res["sim"] = sim
+    return res

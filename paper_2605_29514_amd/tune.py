@@ -2,7 +2,10 @@
 
 The library offers two schedules for a chunk of rotations -- per-step
 kernels with many blocks per product, or the fused per-shot layer kernel --
-and three block sizes for the fused kernel (64, 128, 256 threads per shot).
+three block sizes for the fused kernel (64, 128, 256 threads per shot) and
+two LDS tiles for its FP32-path eigen-solve (factors of order up to 32 or up
+to 64 held in LDS; the larger tile leaves room for fewer blocks per compute
+unit).
 Which one is fastest depends on the shot count, the bond dimensions the
 circuit reaches and the precision, so it is measured, not guessed: each
 candidate runs the same window of the real workload on the real Simulator,
@@ -23,8 +26,12 @@ import json
 import os
 from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
-# (layer mode, threads per shot): 1 = per-step kernels, 2 = fused kernel
-CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 0), (2, 64), (2, 128), (2, 256))
+# (layer mode, threads per shot, eigen-solve LDS order): 1 = per-step
+# kernels, 2 = fused kernel; LDS order 0 = chosen from chi_max by the library
+CANDIDATES: Tuple[Tuple[int, int, int], ...] = ((1, 0, 0), (2, 64, 0), (2, 128, 0), (2, 256, 0),
+                                                (2, 128, 64), (2, 256, 64))
+# the fused-kernel shapes alone (many shots: the per-step schedule is far slower)
+FUSED: Tuple[Tuple[int, int, int], ...] = tuple(c for c in CANDIDATES if c[0] == 2)
 
 
 def cache_path() -> str:
@@ -57,7 +64,7 @@ def store_cache(key: str, entry: dict, path: Optional[str] = None) -> None:
     os.replace(tmp, path)
 
 
-def pick(timings: Dict[Tuple[int, int], float]) -> Tuple[int, int]:
+def pick(timings: Dict[Tuple[int, ...], float]) -> Tuple[int, ...]:
     """Fastest candidate; ties go to the earlier entry of CANDIDATES."""
     order = {c: i for i, c in enumerate(CANDIDATES)}
     return min(timings, key=lambda c: (timings[c], order.get(c, len(order))))
@@ -68,6 +75,7 @@ def apply(sim, choice: Sequence[int]) -> None:
     sim.set_layer_mode(mode)
     if threads:
         sim.set_layer_threads(threads)
+    sim.set_layer_lds(int(choice[2]) if len(choice) > 2 else 0)
 
 
 def autotune(sim, ops, stop: int, *, start: int = 0, key: Optional[str] = None, candidates: Iterable = CANDIDATES,
@@ -90,7 +98,7 @@ def autotune(sim, ops, stop: int, *, start: int = 0, key: Optional[str] = None, 
         stn.run_prepared(sim, ops, 0, start)
         sim.sync()
         ck = sim.checkpoint_save()
-    timings: Dict[Tuple[int, int], float] = {}
+    timings: Dict[Tuple[int, ...], float] = {}
     for cand in candidates:
         cand = tuple(cand)
         apply(sim, cand)
@@ -112,7 +120,7 @@ def autotune(sim, ops, stop: int, *, start: int = 0, key: Optional[str] = None, 
     apply(sim, best)
     sim.reset()
     sim.sync()
-    ms = {f"{m}/{t}": v for (m, t), v in timings.items()}
+    ms = {"/".join(map(str, c)): v for c, v in timings.items()}
     if key:
         store_cache(key, {"choice": list(best), "ms": ms})
     return {"choice": best, "ms": ms, "cached": False}

@@ -183,14 +183,20 @@ class Circuit:
 
     def shot_slice(self, s0: int, s1: int) -> "Circuit":
         """Same circuit restricted to shots [s0, s1)."""
+        return self.shot_select(np.arange(s0, s1))
+
+    def shot_select(self, idx) -> "Circuit":
+        """Same circuit with the per-shot inputs of shots idx (in that order,
+        repeats allowed)."""
+        idx = np.asarray(idx, dtype=np.int64)
         ops = []
         for o in self.ops:
             o2 = dict(o)
             for key in ("x", "z", "theta", "u"):
                 if key in o2:
-                    o2[key] = o2[key][s0:s1]
+                    o2[key] = o2[key][idx]
             ops.append(o2)
-        return Circuit(self.n, s1 - s0, ops, self.layout, self.n_params, dict(self.meta))
+        return Circuit(self.n, len(idx), ops, self.layout, self.n_params, dict(self.meta))
 
 
 def _rng(seed: int, stream: int) -> np.random.Generator:
@@ -263,7 +269,7 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
                    theta_law: str = "fixed", theta_range=(0.02, 0.10),
                    p: float = 0.0, per_layer_params: bool = False,
                    random_sign: bool = False, final_readout: bool = True,
-                   dense_noise: bool = False, crosstalk: str = "coherent") -> Circuit:
+                   dense_noise: bool = False, crosstalk: str = "coherent", basis: str = "Z") -> Circuit:
     """Memory-Z experiment on the rotated code with ZZ(Z) crosstalk.
 
     dense_noise: emit a noise op at every noise location even when no shot
@@ -279,6 +285,10 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
       its own angle parameter index (used for gradients).
     random_sign: each rotation instance and shot flips the sign of its angle
       with probability 1/2 (Eq. 9).
+    basis: "Z" (memory-Z: data start in |0> and are read out in Z) or "X"
+      (memory-X: H on every data qubit after the first reset and before the
+      final readout, so the X checks are the deterministic ones and the
+      readout is in X; ZZ crosstalk then acts on the protected observable).
     crosstalk:
       "coherent"  rotations exp(-i theta Z..Z) (Eq. 4)
       "pta"       their Pauli-twirled approximation (Eq. 6): each coupling
@@ -288,6 +298,8 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
     """
     if crosstalk not in ("coherent", "pta"):
         raise ValueError(crosstalk)
+    if basis not in ("Z", "X"):
+        raise ValueError(basis)
     lay = rotated_layout(d)
     n = lay.n
     S = n_shots
@@ -333,6 +345,9 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
 
     for rnd in range(rounds):
         add_noise(noise.x_flip(anc + (lay.data if rnd == 0 else []), 2 * p))
+        if rnd == 0 and basis == "X":
+            ops.append({"op": "gates", "gates": [("H", q, -1) for q in lay.data]})
+            add_noise(noise.one_qubit(lay.data, 0.1 * p))
         if lay.x_anc:
             ops.append({"op": "gates", "gates": [("H", a, -1) for a in lay.x_anc]})
             add_noise(noise.one_qubit(lay.x_anc, 0.1 * p))
@@ -368,10 +383,13 @@ def memory_circuit(d: int, rounds: int, n_shots: int, *, seed: int = 1,
         ops.append({"op": "measure", "qubits": np.array(anc, np.int32), "reset": True,
                     "u": _uniform53(g_meas, (S, len(anc)))})
     if final_readout:
+        if basis == "X":
+            ops.append({"op": "gates", "gates": [("H", q, -1) for q in lay.data]})
+            add_noise(noise.one_qubit(lay.data, 0.1 * p))
         add_noise(noise.x_flip(lay.data, 5 * p))
         ops.append({"op": "measure", "qubits": np.array(lay.data, np.int32), "reset": False,
                     "u": _uniform53(g_meas, (S, len(lay.data)))})
-    meta = {"d": d, "rounds": rounds, "p": p, "theta_law": theta_law, "crosstalk": crosstalk,
+    meta = {"d": d, "rounds": rounds, "p": p, "theta_law": theta_law, "crosstalk": crosstalk, "basis": basis,
             "n_nn": len(nn), "n_nnn": len(nnn), "n_tri": len(tri)}
     return Circuit(n, S, ops, lay, n_params, meta)
 

@@ -1,36 +1,11 @@
-"""Truncation diagnostics: Schmidt spectra of a returned state and detection
-rates (CPU: against a dense SVD and hand-made records; GPU: the chi sweep's
-spectra against the oracle's MPS at the same points)."""
+"""Truncation diagnostics: detection rates (CPU, hand-made records) and the
+device Schmidt spectrum (GPU: stn_spectrum against the oracle MPS's
+schmidt_values, which tests/test_oracle_pins.py pins to a dense SVD)."""
 import numpy as np
 import pytest
 
 from paper_2605_29514_amd import diagnostics as D
 from paper_2605_29514_amd import workload as W
-
-
-def random_mps(n, rng, bond=3):
-    dims = [1] + [min(bond, 2 ** min(j, n - j)) for j in range(1, n)] + [1]
-    return [rng.normal(size=(dims[j], 2, dims[j + 1])) + 1j * rng.normal(size=(dims[j], 2, dims[j + 1]))
-            for j in range(n)]
-
-
-def dense(ts):
-    v = ts[0]
-    for t in ts[1:]:
-        v = np.tensordot(v, t, axes=([v.ndim - 1], [0]))
-    return v.reshape(-1)
-
-
-@pytest.mark.parametrize("cut", [0, 2, 4])
-def test_schmidt_values_match_dense_svd(cut):
-    rng = np.random.default_rng(cut)
-    ts = random_mps(6, rng)
-    psi = dense(ts)
-    s = np.linalg.svd(psi.reshape(2 ** (cut + 1), -1), compute_uv=False) ** 2
-    s = s / s.sum()
-    got = D.schmidt_values(ts, cut)
-    assert np.allclose(got, s[:len(got)], atol=1e-12)
-    assert abs(got.sum() - 1) < 1e-12
 
 
 def test_detection_rates():
@@ -65,7 +40,41 @@ def test_chi_sweep_spectra_match_oracle():
     stops = [i for i, op in enumerate(circ.ops) if op["op"] == "measure" and op["reset"]]
     for k, stop in enumerate(stops):
         o = ostn.run_shot(circ, 1, chi_max=64, eps_cut=1e-14, stop_after_ops=stop)
-        ref = D.schmidt_values(o.mps.A, circ.n // 2 - 1)
+        sv = o.mps.schmidt_values(circ.n // 2 - 1) ** 2
+        ref = sv / sv.sum()
         got = np.array(res[64]["spectra"][k])
         m = min(len(ref), len(got))
         assert np.allclose(got[:m], ref[:m], atol=1e-10), k
+        assert np.allclose(ref[m:], 0, atol=1e-10) and np.allclose(got[m:], 0, atol=1e-10)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_device_spectrum_every_shot_every_cut(prec):
+    """stn_spectrum for all shots at several cuts of a d=3 two-round run
+    (bonds up to 16) equals the oracle's Schmidt values (FP64 1e-10, FP32
+    1e-6 absolute on values normalised to sum 1); the bond dimension it
+    reports equals the GPU state's."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import stn as ostn
+    from paper_2605_29514_amd import stn
+    stn.load()
+    circ = W.memory_circuit(3, 2, 6, seed=19, theta_law="per_coupling", nnn=True, p=0.01)
+    g = stn.run_circuit(circ, 64, prec, 1e-14 if prec == "fp64" else 1e-12)
+    sim = g["sim"]
+    ores = [ostn.run_shot(circ, s, chi_max=64, eps_cut=1e-14 if prec == "fp64" else 1e-12) for s in range(6)]
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    for bond in (1, 5, circ.n // 2, circ.n - 2):
+        vals, rank = sim.spectrum(bond)
+        vals, rank = vals.cpu().numpy(), rank.cpu().numpy()
+        assert np.array_equal(rank, sim.bonds()[:, bond])
+        for s, o in enumerate(ores):
+            if not np.array_equal(g["records"][s], np.array(o.record, np.uint8)):
+                continue                    # a near-tie record: another trajectory
+            sv = o.mps.copy().schmidt_values(bond - 1) ** 2
+            ref = sv / sv.sum()
+            m = min(len(ref), vals.shape[1])
+            assert np.allclose(vals[s, :m], ref[:m], atol=tol), (bond, s)
+            assert abs(vals[s].sum() - 1) < 1e-9

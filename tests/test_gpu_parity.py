@@ -20,10 +20,33 @@ pytestmark = pytest.mark.gpu
 
 EPS = {"fp64": 1e-14, "fp32": 1e-12}
 PTOL = {"fp64": 1e-10, "fp32": 1e-5}
-# Shots whose worst binding cut has s_k^2 / (s_k^2 - s_{k+1}^2) above this are
-# ill-conditioned at the working precision (the kept subspace turns by about
-# rounding / gap) and are reported, not compared strictly.
-MAX_SENS = {"fp64": 1e6, "fp32": 30.0}
+# A binding cut with sensitivity s_k^2 / (s_k^2 - s_{k+1}^2) turns the kept
+# subspace by about rounding x sensitivity.  Shots whose worst binding cut
+# keeps that below the bar are compared strictly; the others are reported
+# (count printed), not compared.  FP32: unit roundoff 2^-24.
+EPS32 = 2.0 ** -24
+
+
+def fp32_sens_limit():
+    return PTOL["fp32"] / EPS32
+
+
+MAX_SENS = {"fp64": 1e6, "fp32": PTOL["fp32"] / EPS32}
+# Where chi_max binds, each binding projector of the FP32 path is perturbed by
+# the rounding of the FP32 products that feed its reduced density (a few
+# units of 2^-24 for products of length up to 2 chi_max: taken as 4) and turns
+# by that times its sensitivity; a probability moves by at most twice the
+# turn, and the turns of successive cuts add at worst linearly.  So an FP32
+# probability may differ from the oracle's by up to 8 x 2^-24 x (summed
+# sensitivity over the shot's binding cuts): the bar for that shot is the
+# larger of this and 1e-5 (1e-5 itself wherever chi_max does not bind).
+FP32_STEP_ULPS = 4.0
+
+
+def ptol_shot(prec, res):
+    if prec == "fp64":
+        return PTOL[prec]
+    return max(PTOL[prec], 2.0 * FP32_STEP_ULPS * EPS32 * res.cut_sensitivity_sum)
 
 
 def say(*a):
@@ -94,21 +117,24 @@ def run_parity(B, circ, chi, prec, shots, *, check_mps=True, tie=None, mode=0):
     forced = np.array([ores[s].record if s in ores else g["records"][s]
                        for s in range(circ.n_shots)], np.uint8)
     gf = B.run_circuit(circ, chi, prec, eps, forced=forced, layer_mode=lm, layer_threads=nt)
-    worst = 0.0
+    worst, worst_tol = 0.0, PTOL[prec]
     for s in shots:
         po = np.array(ores[s].prob)
         pg = gf["prob"][s]
-        rel = np.abs(pg - po) / po
-        worst = max(worst, float(rel.max()))
-        assert abs(gf["logp"][s] - ores[s].logp) <= PTOL[prec] * max(1.0, abs(ores[s].logp)) * 10
-    assert worst <= PTOL[prec], f"max relative probability error {worst:.3e}"
+        rel = float(np.max(np.abs(pg - po) / po))
+        tol = ptol_shot(prec, ores[s])
+        assert rel <= tol, f"shot {s}: max relative probability error {rel:.3e} above {tol:.3e}"
+        worst, worst_tol = max(worst, rel), max(worst_tol, tol)
+        assert abs(gf["logp"][s] - ores[s].logp) <= tol * max(1.0, abs(ores[s].logp)) * 10
     if mism == 0:
         check_tableau(g["sim"], ores, shots)
         if check_mps:
             for s in shots:
                 f = mps_fidelity(g["sim"], s, ores[s].mps)
-                assert f <= (1e-10 if prec == "fp64" else 1e-5), f"shot {s} fidelity deficit {f:.3e}"
-    say(f"  ok: max rel p err {worst:.2e}, near-tie records {mism}, ill-conditioned shots {skipped}")
+                assert f <= ptol_shot(prec, ores[s]), f"shot {s} fidelity deficit {f:.3e}"
+    say(f"  ok: max rel p err {worst:.2e} (largest per-shot bar {worst_tol:.2e}), near-tie records {mism}, "
+        f"ill-conditioned shots {skipped} "
+        f"of {skipped + len(shots)} (sensitivity above {MAX_SENS[prec]:.3g})")
     return g, ores, worst
 
 
@@ -207,6 +233,14 @@ def test_layer_modes_agree(B, prec, threads):
     a = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=1)
     b = B.run_circuit(circ, 8, prec, EPS[prec], layer_mode=2, layer_threads=threads)
     same = np.all(a["records"] == b["records"], axis=1)
+    # a shot whose records differ must differ first at a near tie: the two
+    # schedules agree on the history up to there, so p(0) is the same to
+    # rounding, and only |u - p(0)| below the tie bound lets them choose apart
+    tie = 1e-9 if prec == "fp64" else 1e-4
+    for s in np.nonzero(~same)[0]:
+        k = int(np.nonzero(a["records"][s] != b["records"][s])[0][0])
+        p0 = a["prob"][s, k] if a["records"][s, k] == 0 else 1.0 - a["prob"][s, k]
+        assert abs(_uniform_of(circ, s, k) - p0) <= tie, f"shot {s}: schedules differ at {k}, not a near tie"
     assert same.mean() > 0.95
     rel = np.abs(a["prob"][same] - b["prob"][same]) / a["prob"][same]
     assert rel.max() <= (2e-10 if prec == "fp64" else 2e-5)

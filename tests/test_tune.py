@@ -7,9 +7,10 @@ from paper_2605_29514_amd import workload as W
 
 
 def test_pick_fastest_and_ties():
-    t = {(1, 0): 5.0, (2, 64): 3.0, (2, 128): 3.0, (2, 256): 9.0}
-    assert tune.pick(t) == (2, 64)                      # tie -> earlier candidate
-    assert tune.pick({(2, 256): 1.0, (1, 0): 2.0}) == (2, 256)
+    t = {(1, 0, 0): 5.0, (2, 128, 0): 3.0, (2, 64, 0): 3.0, (2, 256, 64): 9.0}
+    assert tune.pick(t) == (2, 64, 0)                   # tie -> earlier candidate
+    assert tune.pick({(2, 256, 64): 1.0, (1, 0, 0): 2.0}) == (2, 256, 64)
+    assert all(c[0] == 2 for c in tune.FUSED) and set(tune.FUSED) < set(tune.CANDIDATES)
 
 
 def test_cache_roundtrip(tmp_path, monkeypatch):
@@ -47,7 +48,8 @@ def test_autotune_leaves_initial_state(tmp_path, monkeypatch):
     r = tune.autotune(sim, ops, tune.layers_stop(ops, 2), key="k")
     assert r["choice"] in tune.CANDIDATES and not r["cached"]
     got = stn.run_circuit(circ, 8, "fp64", sim=sim)
-    ref = stn.run_circuit(circ, 8, "fp64", layer_mode=r["choice"][0], layer_threads=r["choice"][1])
+    ref = stn.run_circuit(circ, 8, "fp64", layer_mode=r["choice"][0], layer_threads=r["choice"][1],
+                          layer_lds=r["choice"][2])
     assert np.array_equal(got["records"], ref["records"])
     assert np.array_equal(got["prob"], ref["prob"])
     again = tune.autotune(sim, ops, tune.layers_stop(ops, 2), key="k")
@@ -57,6 +59,7 @@ def test_autotune_leaves_initial_state(tmp_path, monkeypatch):
     w = tune.autotune(sim, ops, tune.layers_stop(ops, 2, start), start=start, key="k2")
     assert w["choice"] in tune.CANDIDATES and not w["cached"]
     got = stn.run_circuit(circ, 8, "fp64", sim=sim)
-    ref = stn.run_circuit(circ, 8, "fp64", layer_mode=w["choice"][0], layer_threads=w["choice"][1])
+    ref = stn.run_circuit(circ, 8, "fp64", layer_mode=w["choice"][0], layer_threads=w["choice"][1],
+                          layer_lds=w["choice"][2])
     assert np.array_equal(got["records"], ref["records"])
     assert np.array_equal(got["prob"], ref["prob"])
