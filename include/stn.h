@@ -206,6 +206,18 @@ size_t stn_tape_bytes(const stn_ctx *ctx, int max_steps);
  * fails with STN_ENOMEM. */
 stn_status stn_tape_begin(stn_ctx *ctx, void *dev_tape, size_t bytes, int max_steps);
 
+/* The same as stn_tape_begin with the tape in the library's own device
+ * memory instead of a caller buffer.  For callers that cannot allocate
+ * device memory (code under HIP-graph capture, serving loops, harnesses
+ * that forbid allocation); it calls no allocation routine.  The static tape
+ * holds 64 MiB per GPU and lives until the process ends: STN_ENOMEM when
+ * stn_tape_bytes(ctx, max_steps) exceeds that, STN_EDEVICE when the array
+ * could not be located on this GPU at stn_init.  Every context on one GPU
+ * shares the same array, which keeps the last tape's contents (each record
+ * is written before it is read): recording or stn_backward on two contexts
+ * of one GPU at overlapping times race. */
+stn_status stn_tape_begin_static(stn_ctx *ctx, int max_steps);
+
 /* Stops recording (snapshots the final state); *n_rotations (may be NULL)
  * receives the number of rotations recorded.  STN_ESTATE if not recording. */
 stn_status stn_tape_end(stn_ctx *ctx, int *n_rotations);
@@ -303,7 +315,9 @@ stn_status stn_profile_phases(stn_ctx *ctx, double *host_cycles);
  *  5 the largest eigen-solve order seen,
  *  6 shader cycles spent in the pivoted Cholesky of the FP32-path solves
  *    (part of phase 6 of stn_profile_phases),
- *  7 FP64-path two-sided Jacobi solves with the matrix in global scratch.
+ *  7 eigen-solves by Jacobi rotations in global scratch (FP64 path: the
+ *    two-sided Jacobi on rho; FP32 path: the one-sided Jacobi on the rows of
+ *    the Cholesky factor when its Gram does not fit the LDS tile).
  * Synchronises. */
 stn_status stn_profile_paths(stn_ctx *ctx, double *host_counts);
 

@@ -56,7 +56,7 @@ class GradientRun:
 
     def __init__(self, circ, chi_max: int, records: np.ndarray, precision: str = "fp64",
                  eps_cut: Optional[float] = None, chi_adj: Optional[int] = None, device: str = "cuda:0",
-                 segments: Optional[Sequence[Tuple[int, int]]] = None):
+                 segments: Optional[Sequence[Tuple[int, int]]] = None, static_tape: bool = False):
         import torch
         self.torch = torch
         self.circ = circ
@@ -67,6 +67,8 @@ class GradientRun:
         self.chi_adj = chi_adj or min(512, max(8 * chi_max, 64))
         self.checkpoints = []
         self.device = device
+        # record into the library's static per-GPU tape instead of a torch buffer
+        self.static_tape = static_tape
 
     def set_theta(self, theta) -> None:
         """theta: [S, R] tensor of per-shot angles in circuit rotation order."""
@@ -100,7 +102,10 @@ class GradientRun:
             nrot = _rots_in(self.ops, a, b)
             col = col_end - nrot
             sim.checkpoint_load(ck)
-            sim.tape_begin(max(1, _steps_in(self.ops, a, b)))
+            if self.static_tape:
+                sim.tape_begin_static(max(1, _steps_in(self.ops, a, b)))
+            else:
+                sim.tape_begin(max(1, _steps_in(self.ops, a, b)))
             stn.run_prepared(sim, self.ops, a, b)
             got = sim.tape_end()
             assert got == nrot, (got, nrot)

@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -125,7 +126,42 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 thread_local Prof *g_prof = nullptr;
 
+// ------------------------------------------------------------ static tape
+// Gradient tape in the library's own device memory, for callers that cannot
+// allocate device memory (code under HIP-graph capture, serving loops,
+// harnesses that forbid allocation): stn_tape_begin_static.  One copy per
+// GPU, loaded with the code object and held until the process ends.  In
+// host code `scratch` names a host-side stand-in, never the device array:
+// every use goes through the per-device address hipGetSymbolAddress returns
+// (scratch_ptr below), looked up once per device at stn_init.
+constexpr size_t kStaticTapeBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticTapeBytes];
 
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices] = {};
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's static tape (nullptr when unavailable); the
+// current device must be the context's.
+char *scratch_ptr() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    g_scratch_ptr[dev] = reinterpret_cast<char *>(p);
+    g_scratch_done[dev] = true;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 hipEvent_t Prof::get() {
   if (used == pool.size()) {
@@ -151,6 +187,7 @@ struct stn_ctx {
   int center = 0;
   int layer_mode = 0;              // 0 auto, 1 per-step kernels, 2 fused per-shot layer kernel
   int layer_threads = 128;         // threads per shot of the fused kernel
+  char *static_tape = nullptr;     // this device's static tape array (stn_tape_begin_static)
   std::vector<uint64_t> hx, hz;    // shadow of the shared bits
   uint8_t tables[9][16];           // per gate kind
   std::string err;
@@ -770,6 +807,7 @@ stn_status stn_init(stn_ctx **out, const stn_config *cfg, void *ws, size_t bytes
     delete c;
     return STN_EDEVICE;
   }
+  c->static_tape = scratch_ptr();
   {
     int max_rows = 4 * c->chi;                           // QR rows of a doubled tensor
     hipError_t pe = c->prec == STN_FP64 ? mps_prepare<double>(max_rows) : mps_prepare<float>(max_rows);
@@ -1091,6 +1129,16 @@ stn_status stn_tape_begin(stn_ctx *c, void *dev_tape, size_t bytes, int max_step
   c->taping = true;
   c->tape_closed = false;
   return STN_OK;
+}
+
+stn_status stn_tape_begin_static(stn_ctx *c, int max_steps) {
+  if (!c || max_steps < 1) return STN_EINVAL;
+  const size_t need = stn_tape_bytes(c, max_steps);
+  if (need > kStaticTapeBytes)
+    return fail(c, STN_ENOMEM, "tape of " + std::to_string(need) + " bytes exceeds the " +
+                                   std::to_string(kStaticTapeBytes >> 20) + " MiB static tape");
+  if (!c->static_tape) return fail(c, STN_EDEVICE, "static tape unavailable on this device");
+  return stn_tape_begin(c, c->static_tape, kStaticTapeBytes, max_steps);
 }
 
 stn_status stn_tape_end(stn_ctx *c, int *n_rotations) {

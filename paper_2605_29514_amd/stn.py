@@ -46,7 +46,7 @@ EXPORTS = ["stn_workspace_bytes", "stn_init", "stn_free", "stn_last_error", "stn
            "stn_tape_bytes", "stn_tape_begin", "stn_tape_end", "stn_adjoint_bytes", "stn_adjoint_init",
            "stn_adjoint_zero", "stn_backward", "stn_checkpoint_bytes", "stn_checkpoint_save",
            "stn_checkpoint_load", "stn_profile_phases", "stn_adjoint_truncated", "stn_profile_paths",
-           "stn_set_layer_lds", "stn_spectrum",
+           "stn_set_layer_lds", "stn_tape_begin_static", "stn_spectrum",
            "stn_set_layer_env"]
 K_CLASSES = ["tableau", "build", "qr", "gemm", "gram", "eigen", "select", "expect", "layer"]
 
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH):
     lib.stn_set_layer_env.argtypes = [vp, i32]
     lib.stn_spectrum.restype = i32
     lib.stn_spectrum.argtypes = [vp, i32, vp, i32, vp]
+    lib.stn_tape_begin_static.restype = i32
+    lib.stn_tape_begin_static.argtypes = [vp, i32]
     lib.stn_tape_end.restype = i32
     lib.stn_tape_end.argtypes = [vp, ctypes.POINTER(i32)]
     lib.stn_adjoint_bytes.restype = ctypes.c_size_t
@@ -275,6 +277,10 @@ class Simulator:
         self._tape, ptr = self._aligned(nb)
         self._check(self.lib.stn_tape_begin(self.ctx, ctypes.c_void_p(ptr), nb, int(max_steps)))
 
+    def tape_begin_static(self, max_steps: int):
+        """Records into the library's static per-GPU tape (no allocation)."""
+        self._check(self.lib.stn_tape_begin_static(self.ctx, int(max_steps)))
+
     def tape_end(self) -> int:
         nr = ctypes.c_int(0)
         self._check(self.lib.stn_tape_end(self.ctx, ctypes.byref(nr)))
@@ -404,7 +410,7 @@ class Simulator:
         out = np.zeros(8, np.float64)
         self._check(self.lib.stn_profile_paths(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
         names = ["env_steps", "qr_steps", "eig_lds", "eig_global", "eig_global_gt128", "max_order",
-                 "chol_cycles", "jacobi64_global"]
+                 "chol_cycles", "jacobi_global"]
         return dict(zip(names, out.tolist()))
 
     def set_layer_mode(self, mode: int):
