@@ -547,6 +547,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
             __syncthreads();
           }
         } else {
+          if (m.prof && tid == 0) atomicAdd(&m.work[kPathBase + kPathJacGlobal], 1.0);
           for (int q = tid; q < rk; q += NT) f.piv[q] = q;
           __syncthreads();
           fe += jac_rows<NT>(nn, rk, Rs, nn, ev, V, m.err, f.piv, f.pos, f.dg, sweeps, eig_conv_tol<T>(),

@@ -837,10 +837,18 @@ __device__ double jac_rows(int nn, int r, c64 *G, int ld, double *ev, c64 *Vout,
                 }
               }
             } else {
-              for (int j = li; j < nn; j += TPP) {
-                const c64 xv = X[j], yv = Y[j];
-                X[j] = cs * xv - sg * yv;
-                Y[j] = sgc * xv + cs * yv;
+              // two elements of each row per step, loads before stores
+              for (int j0 = li; j0 < nn; j0 += 2 * TPP) {
+                const int j1 = j0 + TPP;
+                const c64 x0 = X[j0], y0 = Y[j0];
+                c64 x1 = mk<double>(0, 0), y1 = mk<double>(0, 0);
+                if (j1 < nn) { x1 = X[j1]; y1 = Y[j1]; }
+                X[j0] = cs * x0 - sg * y0;
+                Y[j0] = sgc * x0 + cs * y0;
+                if (j1 < nn) {
+                  X[j1] = cs * x1 - sg * y1;
+                  Y[j1] = sgc * x1 + cs * y1;
+                }
               }
             }
             if (li == 0) {

@@ -22,9 +22,10 @@ from test_gpu_parity import EPS, B, check_tableau, mps_fidelity, ptol_shot, say,
 pytestmark = pytest.mark.gpu
 
 
-def run_counted(B, circ, chi, prec, mode, forced=None, env=None):
+def run_counted(B, circ, chi, prec, mode, forced=None, env=None, lds=0):
     lm, nt = mode
-    sim = B.Simulator(circ.n, circ.n_shots, chi, prec, EPS[prec], "cuda:0", layer_mode=lm, layer_threads=nt)
+    sim = B.Simulator(circ.n, circ.n_shots, chi, prec, EPS[prec], "cuda:0", layer_mode=lm, layer_threads=nt,
+                      layer_lds=lds)
     if env is not None:
         sim.set_layer_env(env)
     sim.profile(["layer", "expect"], counters=True)
@@ -34,7 +35,7 @@ def run_counted(B, circ, chi, prec, mode, forced=None, env=None):
     return g, paths
 
 
-def parity_large(B, circ, chi, prec, shots, mode, env=None):
+def parity_large(B, circ, chi, prec, shots, mode, env=None, lds=0):
     say(f"large-bond parity n={circ.n} S={circ.n_shots} chi={chi} {prec} mode {mode}")
     eps = EPS[prec]
     ores = {s: ostn.run_shot(circ, s, chi_max=chi, eps_cut=eps) for s in shots}
@@ -43,7 +44,7 @@ def parity_large(B, circ, chi, prec, shots, mode, env=None):
     say(f"  oracle max bonds {[max(ores[s].bond_trace) for s in shots]}, sensitivities "
         f"{[round(ores[s].cut_sensitivity, 1) for s in shots]}, compared {len(cmp)} of {len(shots)}")
     assert cmp, "no well-conditioned shot"
-    g, paths = run_counted(B, circ, chi, prec, mode, env=env)
+    g, paths = run_counted(B, circ, chi, prec, mode, env=env, lds=lds)
     tie = 1e-9 if prec == "fp64" else 1e-4
     for s in cmp:
         rg, ro = g["records"][s], np.array(ores[s].record, np.uint8)
@@ -51,7 +52,7 @@ def parity_large(B, circ, chi, prec, shots, mode, env=None):
             k = int(np.nonzero(rg != ro)[0][0])
             assert abs(_uniform_of(circ, s, k) - ores[s].p0[k]) <= tie, f"shot {s}: record differs at {k}"
     forced = np.array([ores[s].record if s in ores else g["records"][s] for s in range(circ.n_shots)], np.uint8)
-    gf, _ = run_counted(B, circ, chi, prec, mode, forced=forced, env=env)
+    gf, _ = run_counted(B, circ, chi, prec, mode, forced=forced, env=env, lds=lds)
     errs = {}
     for s in cmp:
         po = np.array(ores[s].prob)
@@ -77,13 +78,14 @@ def test_environment_path_doubled_bonds_to_256(B, prec):
     assert paths["env_steps"] > 0 and paths["qr_steps"] == 0 and paths["max_order"] == 256
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_environment_path_orders_to_128(B, prec):
-    """Bonds reach 64 (chi_max 64 does not bind): every span's doubled bonds
-    fit the 128-wide environment Grams; eigen-solves of order 65..128 run in
-    global scratch."""
+@pytest.mark.parametrize("prec,lds", [("fp32", 0), ("fp32", 64), ("fp64", 0)])
+def test_environment_path_orders_to_128(B, prec, lds):
+    """Bonds reach 64 (chi_max 64 does not bind): eigen-solves of order
+    65..128 with rho in global scratch.  FP32: ranks up to 42 (LDS tile 32)
+    or 64 (tile 64) take the Gram of the Cholesky factor in LDS, larger ones
+    the one-sided Jacobi on the factor rows in global scratch."""
     circ = entangling_circuit(12, 20, 4, 7, meas_every=6)
-    paths, ores = parity_large(B, circ, 64, prec, range(0, 4), (2, 256))
+    paths, ores = parity_large(B, circ, 64, prec, range(0, 4), (2, 256), lds=lds)
     assert max(max(o.bond_trace) for o in ores.values()) == 64
     assert paths["env_steps"] > 0 and paths["qr_steps"] == 0
     assert paths["eig_global"] > 0 and paths["max_order"] == 128
@@ -103,7 +105,7 @@ def test_qr_path_orders_to_256(B, prec, mode):
     if mode[0] == 2:
         assert paths["qr_steps"] > 0 and paths["eig_global_gt128"] > 0 and paths["max_order"] == 256
         if prec == "fp64":
-            assert paths["jacobi64_global"] > 0
+            assert paths["jacobi_global"] > 0
 
 
 def test_fp32_chi_binding_at_orders_above_64(B):
