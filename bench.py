@@ -68,6 +68,8 @@ CLASS_BOUND = {
 # the machine's CPU share for one GPU: worker pools stay within it whatever the
 # host reports
 HOST_CPU_SHARE = 16
+# autotuner candidates of the bench window: (layer mode, threads per shot, LDS tile)
+BENCH_CANDIDATES = ((2, 256, 0), (2, 256, 64), (2, 512, 0), (2, 512, 64))
 
 
 def kernel_source_hash():
@@ -295,7 +297,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-shot FP64 GPU form (per-step kernels, one shot at a time)")
     ap.add_argument("--plain-shots", type=int, default=4)
-    ap.add_argument("--plain-seconds", type=float, default=45.0,
+    ap.add_argument("--plain-seconds", type=float, default=30.0,
                     help="time budget of the plain FP64 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM byte counters)")
@@ -336,9 +338,11 @@ def main():
     if args.layer_mode == 0 and args.layer_threads == 0 and not args.no_tune:
         from paper_2605_29514_amd import tune
         key = tune.problem_key(torch.cuda.get_device_name(0), circ.n, circ.n_shots, chi, prec, args.config)
-        # the fused shapes only: at this shot count the per-step schedule is
-        # slower by orders of magnitude; each candidate runs one whole step
-        t = tune.autotune(sim, ops, stop, key=f"{key}|window {args.window}", candidates=tune.FUSED,
+        # the fused shapes with 256 or 512 threads per shot: at this shot
+        # count the per-step schedule is slower by orders of magnitude, and
+        # 64 / 128 threads by about 2x on this window (measured); each
+        # candidate runs one whole step
+        t = tune.autotune(sim, ops, stop, key=f"{key}|window {args.window}", candidates=BENCH_CANDIDATES,
                           log=lambda m: print("# " + m, file=sys.stderr, flush=True))
         chosen = tuple(t["choice"])
         schedule = {"layer_mode": chosen[0], "layer_threads": chosen[1], "layer_lds": chosen[2], "tuned": True,

@@ -329,7 +329,7 @@ stn_status stn_profile_paths(stn_ctx *ctx, double *host_counts);
 stn_status stn_set_layer_mode(stn_ctx *ctx, int mode);
 
 /* Threads per shot of the fused layer kernel: 64 (one wavefront per shot),
- * 128 (the default) or 256.  A tuning knob: results agree to rounding order.
+ * 128 (the default), 256 or 512.  A tuning knob: results agree to rounding order.
  * STN_EINVAL for any other value. */
 stn_status stn_set_layer_threads(stn_ctx *ctx, int threads);
 

@@ -1075,7 +1075,7 @@ stn_status stn_set_layer_mode(stn_ctx *c, int mode) {
 }
 
 stn_status stn_set_layer_threads(stn_ctx *c, int threads) {
-  if (!c || (threads != 64 && threads != 128 && threads != 256)) return STN_EINVAL;
+  if (!c || (threads != 64 && threads != 128 && threads != 256 && threads != 512)) return STN_EINVAL;
   c->layer_threads = threads;
   return STN_OK;
 }

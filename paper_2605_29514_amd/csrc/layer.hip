@@ -4,8 +4,8 @@
 // rotations (centre moves, bond-2 operator blocks, left-to-right QR sweep,
 // right-to-left FP64 Gram/eigen truncation, FP64 renormalisation) with block
 // barriers only: one launch per chunk instead of ~10 launches per site, and
-// every shot proceeds at its own bond dimensions.  The block size NT (64, 128
-// or 256 threads per shot) is a launch parameter: with 64 threads a shot is
+// every shot proceeds at its own bond dimensions.  The block size NT (64, 128,
+// 256 or 512 threads per shot) is a launch parameter: with 64 threads a shot is
 // one wavefront and a barrier costs almost nothing, so 1024 shots fill the
 // 1024 SIMDs of the chip; larger blocks give a single shot more lanes when
 // there are few shots or large bonds.
@@ -120,10 +120,16 @@ __device__ inline Fallback fallback(const MpsDev &m, int s) {
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void blk_gemm(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
                          const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, char *lds) {
-  if (M <= kDirectGemm && N <= kDirectGemm && K <= kDirectGemm)
+  // 512 threads: eight waves each take their own 16 x 32 output blocks
+  // straight from memory (the LDS-staged tile is shaped for up to four)
+  if constexpr (NT >= 512) {
     gemm_direct<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc);
-  else
-    gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds + u_off(NT));
+  } else {
+    if (M <= kDirectGemm && N <= kDirectGemm && K <= kDirectGemm)
+      gemm_direct<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc);
+    else
+      gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds + u_off(NT));
+  }
   __syncthreads();
 }
 
@@ -759,7 +765,8 @@ void mps_measure_fused(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *
   KLAUNCH(K_TABLEAU, k_clear_words, dim3(1), dim3(64), 0, st, d_negmask, d_mmask, SW);
   if (nt == 64) launch_meas<T, 64>(m, d_snap_sign, d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, st);
   else if (nt == 128) launch_meas<T, 128>(m, d_snap_sign, d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, st);
-  else launch_meas<T, 256>(m, d_snap_sign, d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, st);
+  else if (nt == 256) launch_meas<T, 256>(m, d_snap_sign, d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, st);
+  else launch_meas<T, 512>(m, d_snap_sign, d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, st);
 }
 
 template <typename T>
@@ -767,22 +774,25 @@ void mps_rot_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_p
                    const double *d_theta, int64_t stride, const RotLayer &L, int nt, hipStream_t st) {
   if (nt == 64) launch_layer<T, 64>(m, d_pbits, d_psgn, W, SW, d_theta, stride, L, st);
   else if (nt == 128) launch_layer<T, 128>(m, d_pbits, d_psgn, W, SW, d_theta, stride, L, st);
-  else launch_layer<T, 256>(m, d_pbits, d_psgn, W, SW, d_theta, stride, L, st);
+  else if (nt == 256) launch_layer<T, 256>(m, d_pbits, d_psgn, W, SW, d_theta, stride, L, st);
+  else launch_layer<T, 512>(m, d_pbits, d_psgn, W, SW, d_theta, stride, L, st);
 }
 
 template <typename T>
 hipError_t layer_prepare() {
   hipError_t e = hipSuccess;
-  const void *fs[12] = {(const void *)k_layer<T, 64, false>, (const void *)k_layer<T, 128, false>,
-                        (const void *)k_layer<T, 256, false>, (const void *)k_meas<T, 64, false>,
-                        (const void *)k_meas<T, 128, false>, (const void *)k_meas<T, 256, false>,
+  const void *fs[16] = {(const void *)k_layer<T, 64, false>, (const void *)k_layer<T, 128, false>,
+                        (const void *)k_layer<T, 256, false>, (const void *)k_layer<T, 512, false>,
+                        (const void *)k_meas<T, 64, false>, (const void *)k_meas<T, 128, false>,
+                        (const void *)k_meas<T, 256, false>, (const void *)k_meas<T, 512, false>,
                         (const void *)k_layer<T, 64, true>, (const void *)k_layer<T, 128, true>,
-                        (const void *)k_layer<T, 256, true>, (const void *)k_meas<T, 64, true>,
-                        (const void *)k_meas<T, 128, true>, (const void *)k_meas<T, 256, true>};
-  const int nts[6] = {64, 128, 256, 64, 128, 256};
-  for (int i = 0; i < 12; ++i) {
+                        (const void *)k_layer<T, 256, true>, (const void *)k_layer<T, 512, true>,
+                        (const void *)k_meas<T, 64, true>, (const void *)k_meas<T, 128, true>,
+                        (const void *)k_meas<T, 256, true>, (const void *)k_meas<T, 512, true>};
+  const int nts[4] = {64, 128, 256, 512};
+  for (int i = 0; i < 16; ++i) {
     hipError_t e2 = hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds_bytes(nts[i % 6], sizeof(T) == 8, kEigLdsMax));
+                                        (int)lds_bytes(nts[i % 4], sizeof(T) == 8, kEigLdsMax));
     if (e == hipSuccess) e = e2;
   }
   return e;

@@ -426,7 +426,7 @@ class Simulator:
         self._check(self.lib.stn_set_layer_env(self.ctx, int(max_bond)))
 
     def set_layer_threads(self, threads: int):
-        """Threads per shot of the fused layer kernel (64, 128 or 256)."""
+        """Threads per shot of the fused layer kernel (64, 128, 256 or 512)."""
         self._check(self.lib.stn_set_layer_threads(self.ctx, int(threads)))
 
 

@@ -2,7 +2,7 @@
 
 The library offers two schedules for a chunk of rotations -- per-step
 kernels with many blocks per product, or the fused per-shot layer kernel --
-three block sizes for the fused kernel (64, 128, 256 threads per shot) and
+four block sizes for the fused kernel (64, 128, 256, 512 threads per shot) and
 two LDS tiles for its FP32-path eigen-solve (factors of order up to 32 or up
 to 64 held in LDS; the larger tile leaves room for fewer blocks per compute
 unit).
@@ -29,7 +29,7 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 # (layer mode, threads per shot, eigen-solve LDS order): 1 = per-step
 # kernels, 2 = fused kernel; LDS order 0 = chosen from chi_max by the library
 CANDIDATES: Tuple[Tuple[int, int, int], ...] = ((1, 0, 0), (2, 64, 0), (2, 128, 0), (2, 256, 0),
-                                                (2, 128, 64), (2, 256, 64))
+                                                (2, 128, 64), (2, 256, 64), (2, 512, 0), (2, 512, 64))
 # the fused-kernel shapes alone (many shots: the per-step schedule is far slower)
 FUSED: Tuple[Tuple[int, int, int], ...] = tuple(c for c in CANDIDATES if c[0] == 2)
 

@@ -92,7 +92,7 @@ def test_environment_path_orders_to_128(B, prec, lds):
 
 
 @pytest.mark.parametrize("prec,mode", [("fp32", (2, 256)), ("fp64", (2, 256)), ("fp32", (2, 128)),
-                                       ("fp64", (1, 0))])
+                                       ("fp32", (2, 512)), ("fp64", (1, 0))])
 def test_qr_path_orders_to_256(B, prec, mode):
     """Bonds reach 128 and eigen-solves order 256.  The environment Grams are
     limited to doubled bonds of 64 here, so wider spans take the QR sweep

@@ -89,8 +89,8 @@ def sched(mode):
     return mode if isinstance(mode, tuple) else (mode, 0)
 
 
-# per-step kernels, fused kernel with one wavefront per shot, fused with 256 threads
-MODES = [(1, 0), (2, 64), (2, 256)]
+# per-step kernels, fused kernel with one wavefront per shot, fused with 256 and 512 threads
+MODES = [(1, 0), (2, 64), (2, 256), (2, 512)]
 
 
 def run_parity(B, circ, chi, prec, shots, *, check_mps=True, tie=None, mode=0):
