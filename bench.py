@@ -69,7 +69,7 @@ CLASS_BOUND = {
 # host reports
 HOST_CPU_SHARE = 16
 # autotuner candidates of the bench window: (layer mode, threads per shot, LDS tile)
-BENCH_CANDIDATES = ((2, 256, 0), (2, 256, 64), (2, 512, 0), (2, 512, 64))
+BENCH_CANDIDATES = ((2, 256, 32), (2, 256, 64), (2, 512, 32), (2, 512, 64))
 
 
 def kernel_source_hash():

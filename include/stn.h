@@ -66,7 +66,12 @@ typedef struct {
                             (Eq. 8).  The squared values come from an FP64 Gram
                             eigen-solve, whose absolute error is a few FP64 epsilons
                             times sum lambda^2: cuts below ~1e-14 let rounding
-                            decide the kept count. */
+                            decide the kept count.  STN_FP32, fused schedule: where
+                            fewer pivots of the pivoted Cholesky factor of the
+                            Gram than chi_max (and 2^min(j, n-j)) stay above
+                            eps_cut * trace, those pivot rows span the kept space
+                            (no eigen-solve); each direction left out then holds
+                            at most eps_cut * trace. */
     void *stream;        /* hipStream_t, or NULL for the default stream */
 } stn_config;
 
@@ -305,7 +310,7 @@ stn_status stn_profile_phases(stn_ctx *ctx, double *host_cycles);
 
 /* Branch counters of the fused layer kernel while profiling is on with
  * counters (stn_profile without STN_PROFILE_TIMING_ONLY), summed over shots
- * since the last stn_profile call; host_counts: 8 doubles, in order:
+ * since the last stn_profile call; host_counts: 9 doubles, in order:
  *  0 two-term steps whose left-to-right sweep formed left-environment Grams,
  *  1 steps that took the Householder QR sweep instead (a doubled bond of the
  *    span above the environment limit),
@@ -317,7 +322,10 @@ stn_status stn_profile_phases(stn_ctx *ctx, double *host_cycles);
  *    (part of phase 6 of stn_profile_phases),
  *  7 eigen-solves by Jacobi rotations in global scratch (FP64 path: the
  *    two-sided Jacobi on rho; FP32 path: the one-sided Jacobi on the rows of
- *    the Cholesky factor when its Gram does not fit the LDS tile).
+ *    the Cholesky factor when its Gram does not fit the LDS tile),
+ *  8 FP32-path truncations of rho in global scratch decided by the relative
+ *    cut alone, whose kept space came from the orthonormalised leading rows
+ *    of the pivoted Cholesky factor (no eigen-solve).
  * Synchronises. */
 stn_status stn_profile_paths(stn_ctx *ctx, double *host_counts);
 
@@ -340,12 +348,16 @@ stn_status stn_set_layer_threads(stn_ctx *ctx, int threads);
  * order. */
 stn_status stn_set_layer_env(stn_ctx *ctx, int max_bond);
 
-/* LDS tile of the fused layer kernel's FP32-path eigen-solve: truncation
- * steps of order up to `order` (32 or 64) keep the factor in LDS (larger ones
- * use the shot's global scratch); 0 = chosen from chi_max (64 when
- * 17 <= chi_max <= 32, else 32).  The 64 tile takes ~70 KB of LDS per block,
- * so fewer shots are resident per compute unit.  A tuning knob: results
- * agree to rounding order.  STN_EINVAL for any other value. */
+/* LDS tile of the fused layer kernel's FP32-path truncation: steps of order
+ * up to `order` (32 or 64) keep the factor in LDS, and larger steps whose
+ * pivoted-Cholesky rank (or count above the cut) fits the tile solve its
+ * Gram there (larger ones use the shot's global scratch); 0 = chosen from
+ * chi_max and the threads per shot (64 when 17 <= chi_max <= 32 or with 256
+ * or more threads, else 32).  The 64 tile takes ~70 KB of LDS per block,
+ * so fewer 64- or 128-thread shots are resident per compute unit.  A tuning
+ * knob: results agree within the truncation cut (the kept spaces of a step
+ * may differ by directions of weight below eps_cut).  STN_EINVAL for any
+ * other value. */
 stn_status stn_set_layer_lds(stn_ctx *ctx, int order);
 
 /* Overwrite one MPS site tensor of one shot from the host (synchronises):

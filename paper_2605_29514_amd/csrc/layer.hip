@@ -90,10 +90,14 @@ constexpr int k_gram_order(int en) {
   return r;
 }
 static_assert(k_gram_order(32) >= 40 && k_gram_order(64) == 64, "Gram orders held in LDS");
-// FP32 path: factors up to order 64 in LDS when chi_max is 17..32 (every
-// doubled bond then fits, at ~70 KB per block); otherwise up to 32 (~22 KB)
-// and larger orders in the shot's global scratch.
-inline int eig_lds_order(int chi) { return (2 * chi > 32 && 2 * chi <= kEigLdsMax) ? kEigLdsMax : 32; }
+// FP32 path: factors (and the Grams of global-scratch factors) up to order
+// 64 in LDS (~70 KB per block) when chi_max is 17..32, where every doubled
+// bond then fits, or when a block has 256 or more threads (at most two such
+// blocks share a compute unit: their registers, not LDS, bound residency);
+// otherwise up to 32 (~22 KB, four 128-thread blocks per compute unit).
+inline int eig_lds_order(int chi, int nt) {
+  return nt >= 256 || (2 * chi > 32 && 2 * chi <= kEigLdsMax) ? kEigLdsMax : 32;
+}
 
 // Global fallbacks in the shot's J scratch: reflector vectors for up to
 // 4 chi + 2 rows, eigen-solve index and pair tables for orders up to 2 chi + 2.
@@ -471,6 +475,9 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
       atomicMax(reinterpret_cast<unsigned long long *>(&m.work[kPathBase + kPathMaxOrder]), (unsigned long long)nn);
     }
     long long t_chol = 0;
+    int qk = 0;              // FP32 path, cut decided by the relative cut alone: kept rows in Rs
+    double qw = 0;           // and the discarded fraction of the trace
+    c64 *Rs = reinterpret_cast<c64 *>(scr<T>(m.R, m.R_cap, s));
     {
       const Fallback f = fallback(m, s);
       const bool li = nn <= kEigIdx;
@@ -499,38 +506,51 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         fe = 36.0 * nn * nn * (double)nn;
         Vsel = Gg;
       } else {
-        // FP32 path: pivoted Cholesky + one-sided Jacobi on the factor, on
-        // one matrix in LDS: rho itself when it was formed there, else the
-        // Gram K = Rs Rs^H of
-        // the contiguous factor Rs (r x nn, in the shot's R scratch) that a
-        // left-looking pivoted Cholesky of rho in global scratch produces,
-        // when its rank fits; K has the nonzero eigenvalues of rho, and the
-        // eigenvectors of rho come back as Rs^H u / sqrt(lambda) (a
-        // product).  Past both, one-sided Jacobi on the rows of Rs in
-        // global scratch.  One eig_psd call site serves the LDS cases.
+        // FP32 path: rho formed in LDS (order <= 32) is solved there by
+        // pivoted Cholesky + one-sided Jacobi on the factor.  A larger rho
+        // (global scratch) is factored left-looking into the contiguous rows
+        // Rs (r x nn, the shot's R scratch).  When fewer pivots than
+        // min(chi_max, 2^min(j, n-j)) stay above the relative cut, the cut
+        // alone decides: the kept space is spanned by those leading rows
+        // (their Schur complement, at most the count left times the cut
+        // weight each, is what is dropped), orthonormalised by two passes of
+        // Cholesky QR with their Gram in LDS -- no eigen-solve.  Otherwise
+        // (chi_max or the physical bound binds) the eigenvalues decide: the
+        // Gram K = Rs Rs^H (same nonzero eigenvalues as rho) is solved in
+        // LDS when its order fits and the eigenvectors of rho come back as
+        // Rs^H u / sqrt(lambda), else one-sided Jacobi runs on the rows of
+        // Rs in global scratch.
         const double ct = chol_tol(m.eps_cut, nn);
         double *ev = m.ev + s * m.ev_cap;
         c64 *V = m.V + s * m.V_cap;
         int *piv_l = reinterpret_cast<int *>(lds + kPiv), *pos_l = reinterpret_cast<int *>(lds + kPos);
         double *dg_l = reinterpret_cast<double *>(lds + kDg), *evl = reinterpret_cast<double *>(lds + kEv);
-        c64 *Rs = reinterpret_cast<c64 *>(scr<T>(m.R, m.R_cap, s));
         int eo = -1, rk = 0;
         fe = 0;
         if (vl) {
           eo = nn;
         } else {
-          double tr;
-          rk = chol_rows<NT>(nn, Gg, nn, Rs, nn, ct, f.dg, f.pos, reinterpret_cast<c64 *>(lds + kWp), m.err, &tr,
-                             &fe);
+          double tr, resid;
+          int rc;
+          c64 *wpl = reinterpret_cast<c64 *>(lds + kWp);
+          rk = chol_rows<NT>(nn, Gg, nn, Rs, nn, ct, f.dg, f.pos, wpl, m.err, &tr, &fe, m.eps_cut, &rc, &resid);
           if (clk.on && tid == 0) t_chol = clock64();
-          if (rk >= 1 && rk <= (eig_n > 32 ? k_gram_order(64) : k_gram_order(32))) {
+          const int kt = eig_n > 32 ? k_gram_order(64) : k_gram_order(32);
+          const int eb = j < m.n - j ? j : m.n - j;
+          const int kcap = eb < 30 && (1 << eb) < m.chi ? (1 << eb) : m.chi;
+          if (rc >= 1 && rc <= kcap && rc <= kt && orth_rows<NT>(rc, nn, Rs, nn, V, Gl, rc + 1, wpl, &fe)) {
+            qk = rc;
+            qw = tr > 0 ? resid / tr : 0.0;
+            if (m.prof && tid == 0) atomicAdd(&m.work[kPathBase + kPathCholQr], 1.0);
+          } else if (rk >= 1 && rk <= kt) {
             gemm_direct<double, double, double, double, NT>(rk, rk, nn, Rs, nn, 0, Rs, nn, 1, Gl, rk + 1);
             __syncthreads();
             fe += gemm_flops(rk, rk, nn);
             eo = rk;
           }
         }
-        if (eo >= 0) {
+        if (qk > 0) {
+        } else if (eo >= 0) {
           fe += eig_psd<NT>(eo, Gl, eo + 1, evl, nullptr, m.err, piv_l, pos_l, dg_l, sweeps, ct, eig_conv_tol<T>(),
                             eig_rot_tol<T>(), (vl && clk.on) ? &t_chol : nullptr);
           if (!vl) {
@@ -584,6 +604,9 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
             return rn[row] * cj(Gl[(size_t)pv[row] * ldw + i]);
           },
           Vt);
+    } else if (qk > 0) {
+      // basis vectors of the kept space: the conjugated orthonormal rows
+      k = select_fixed<T, NT>(m, s, j, qk, qw, [&](int i, int c) { return cj(Rs[(size_t)c * nn + i]); }, Vt);
     } else {
       k = select_body<T, NT>(m, s, j, Vsel, Vt);
     }
@@ -727,7 +750,7 @@ __global__ void k_clear_words(uint64_t *a, uint64_t *b, int n) {
 template <typename T, int NT>
 void launch_layer(const MpsDev &m, const uint64_t *d_pbits, const uint64_t *d_psgn, int W, int SW,
                   const double *d_theta, int64_t stride, const RotLayer &L, hipStream_t st) {
-  const int en = m.lds_order ? m.lds_order : eig_lds_order(m.chi);
+  const int en = m.lds_order ? m.lds_order : eig_lds_order(m.chi, NT);
   if (m.prof)
     KLAUNCH(K_LAYER, (k_layer<T, NT, true>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_pbits,
             d_psgn, W, SW, d_theta, stride, L, en);
@@ -748,7 +771,7 @@ template <typename T, int NT>
 void launch_meas(const MpsDev &m, const uint64_t *d_snap_sign, const c64 *d_ops, const c64 *d_eops,
                  const MeasStep &a, const double *d_u, const uint8_t *d_forced, uint8_t *d_out, double *d_prob,
                  uint64_t *d_negmask, uint64_t *d_mmask, hipStream_t st) {
-  const int en = m.lds_order ? m.lds_order : eig_lds_order(m.chi);
+  const int en = m.lds_order ? m.lds_order : eig_lds_order(m.chi, NT);
   if (m.prof)
     KLAUNCH(K_EXPECT, (k_meas<T, NT, true>), dim3(m.S), dim3(NT), lds_bytes(NT, sizeof(T) == 8, en), st, m, d_snap_sign,
             d_ops, d_eops, a, d_u, d_forced, d_out, d_prob, d_negmask, d_mmask, en);

@@ -924,11 +924,15 @@ __device__ double jac_rows(int nn, int r, c64 *G, int ld, double *ev, c64 *Vout,
 // pivot order, with R^H R = A up to the part left out; the Schur diagonal
 // follows each row (d_q -= |R_k[q]|^2).  Stops once d <= chol_tol tr A (the
 // eigenvalues left out are then at most nn chol_tol tr A in total), returns
-// the rank r and (to every thread) tr A in *trace.
+// the rank r and (to every thread) tr A in *trace.  The pivots d never grow
+// from step to step; *r_cut is the number of steps taken while d was above
+// cut_tol tr A (cut_tol >= chol_tol) and *resid the trace of the Schur
+// complement left at that point (tr A minus the squared norms of those rows).
 // Scratch: dg (nn doubles), pos (nn ints), wp (NT complex doubles).
 template <int NT>
 __device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double chol_tol, double *dg, int *pos,
-                         c64 *wp, int *err, double *trace, double *flops) {
+                         c64 *wp, int *err, double *trace, double *flops, double cut_tol, int *r_cut,
+                         double *resid) {
   const int tid = threadIdx.x;
   constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
   __shared__ double amv[2 * NW];
@@ -952,9 +956,17 @@ __device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double 
   int CL, G;
   col_split<NT>(nn, CL, G);
   const int jj = tid % CL, g = tid / CL;
-  int r = 0;
-  double fl = 0;
+  int r = 0, rc = -1;
+  double fl = 0, res = 0;
+  const double cthr = cut_tol * tr;
   for (int k = 0; k < nn; ++k) {
+    if (rc < 0 && !(d > cthr)) {               // uniform: d comes from the block argmax
+      double part = 0;
+      for (int q = tid; q < nn; q += NT)
+        if (pos[q] >= nn) part += dg[q];
+      res = bsum<NT>(part);
+      rc = k;
+    }
     if (!(d > thr) || !(tr > 0)) break;
     const double isd = 1.0 / sqrt(d);
     for (int jb = 0; jb < nn; jb += CL) {
@@ -1006,8 +1018,93 @@ __device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double 
     r = k + 1;
     bargmax<NT>(v, vi, d, p, amv, ami, (k + 1) & 1);
   }
+  if (rc < 0) rc = r;                          // full rank above the cut: nothing left
+  *r_cut = rc;
+  *resid = res;
   *flops += fl;
   return r;
+}
+
+// Cholesky factor of a Hermitian positive definite r x r matrix K in place
+// (ld ldk): right-looking, one barrier per column, the trailing update taken
+// from the unscaled column (K_ij -= K_ik conj(K_jk) / d_k) and every column
+// scaled at the end; the upper triangle is set to zero.  Returns false (to
+// every thread, K partly updated) when a pivot is not positive.
+template <int NT>
+__device__ bool chol_lower(int r, c64 *K, int ldk) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < r; ++k) {
+    const double d = K[(size_t)k * ldk + k].x;
+    if (!(d > 0)) return false;
+    const double id = 1.0 / d;
+    const int t = r - k - 1;
+    for (int e = tid; e < t * t; e += NT) {
+      const int i = k + 1 + e / t, j = k + 1 + e % t;
+      if (j > i) continue;
+      const c64 a = K[(size_t)i * ldk + k], b = K[(size_t)j * ldk + k];
+      K[(size_t)i * ldk + j] = K[(size_t)i * ldk + j] - id * (a * cj(b));
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < r * r; e += NT) {
+    const int i = e / r, j = e % r;
+    if (j > i) K[(size_t)i * ldk + j] = mk<double>(0, 0);
+    else if (j < i) K[(size_t)i * ldk + j] = (1.0 / sqrt(K[(size_t)j * ldk + j].x)) * K[(size_t)i * ldk + j];
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += NT) K[(size_t)i * ldk + i] = mk<double>(sqrt(K[(size_t)i * ldk + i].x), 0);
+  __syncthreads();
+  return true;
+}
+
+// Inverse of a lower-triangular r x r matrix L in place (ld ldk, real
+// positive diagonal, zero upper triangle), row by row: row i of the inverse
+// W is W_ii = 1 / L_ii, W_ij = -(sum_{k=j}^{i-1} L_ik W_kj) / L_ii (j < i),
+// from the rows above (already inverted) and row i of L; row: r complex.
+template <int NT>
+__device__ void trinv_lower(int r, c64 *K, int ldk, c64 *row) {
+  const int tid = threadIdx.x;
+  for (int i = 0; i < r; ++i) {
+    const double il = 1.0 / K[(size_t)i * ldk + i].x;
+    for (int j = tid; j <= i; j += NT) {
+      if (j == i) {
+        row[j] = mk<double>(il, 0);
+      } else {
+        c64 acc = mk<double>(0, 0);
+        for (int k = j; k < i; ++k) acc = acc + K[(size_t)i * ldk + k] * K[(size_t)k * ldk + j];
+        row[j] = (-il) * acc;
+      }
+    }
+    __syncthreads();
+    for (int j = tid; j <= i; j += NT) K[(size_t)i * ldk + j] = row[j];
+    __syncthreads();
+  }
+}
+
+// Orthonormal rows spanning the r rows of R (r x nn, ld ldr, FP64), in
+// place, by two passes of Cholesky QR: K = R R^H = L L^H, R <- L^{-1} R.  A
+// pass leaves a loss of orthogonality of about eps_64 cond(R)^2, which the
+// second pass (on rows already orthogonal to that level) removes; the rows
+// here come from a pivoted Cholesky stopped at a relative pivot of 1e-12
+// or more, so cond(R) stays far below the 1e8 at which that would fail.
+// K: r x r (ld ldk), row: r complex, Tmp: r x nn (ld ldr).  Returns false
+// when a factorisation meets a non-positive pivot; R then holds its input.
+template <int NT>
+__device__ __noinline__ bool orth_rows(int r, int nn, c64 *R, int ldr, c64 *Tmp, c64 *K, int ldk, c64 *row,
+                                      double *flops) {
+  for (int pass = 0; pass < 2; ++pass) {
+    const c64 *src = pass ? Tmp : R;
+    c64 *dst = pass ? R : Tmp;
+    gemm_direct<double, double, double, double, NT>(r, r, nn, src, ldr, 0, src, ldr, 1, K, ldk);
+    __syncthreads();
+    if (!chol_lower<NT>(r, K, ldk)) return false;
+    trinv_lower<NT>(r, K, ldk, row);
+    gemm_direct<double, double, double, double, NT>(r, nn, r, K, ldk, 0, src, ldr, 0, dst, ldr);
+    __syncthreads();
+    // K and the product (8 r^2 nn each), factor and inverse (8 r^3 / 6 each)
+    *flops += 2 * gemm_flops(r, r, nn) + 8.0 * r * r * (double)r / 3.0;
+  }
+  return true;
 }
 
 template <int NT>
@@ -1103,6 +1200,26 @@ __device__ inline double chol_tol(double eps_cut, int nn) { return fmax(eps_cut 
 // (nn x k'); site j <- Vt^H as (k', 2, wb[j+1]); bond[j] = k',
 // bond[j+1] = wb[j+1].  ev: the sorted eigenvalues (nn); vload(i, c):
 // element i of the eigenvector of ev[c].
+// Vt = the k kept columns (nn x k), site j <- Vt^H as (k, 2, wb[j+1]),
+// bond[j] = k, bond[j+1] = wb[j+1].
+template <typename T, int NT, typename VF>
+__device__ void select_store(const MpsDev &m, int s, int j, int k, VF vload, cplx<T> *Vt) {
+  const int *w = wbd(m, s);
+  const int nn = 2 * w[j + 1];
+  cplx<T> *site = slot<T>(m, j, s);
+  blk_each_rc<NT, 4, cplx<T>>(
+      nn, k, [&](int i, int c) { return cvt<T>(vload(i, c)); },
+      [&](int i, int c, cplx<T> v) {
+        Vt[(size_t)i * k + c] = v;
+        site[(size_t)c * nn + i] = cj(v);
+      });
+  if (threadIdx.x == 0) {
+    bnd(m, s)[j] = k;
+    bnd(m, s)[j + 1] = w[j + 1];
+  }
+  __syncthreads();
+}
+
 template <typename T, int NT, typename VF>
 __device__ int select_core(const MpsDev &m, int s, int j, const double *ev, VF vload, cplx<T> *Vt) {
   int *w = wbd(m, s);
@@ -1134,18 +1251,21 @@ __device__ int select_core(const MpsDev &m, int s, int j, const double *ev, VF v
   }
   __syncthreads();
   const int k = kk;
-  cplx<T> *site = slot<T>(m, j, s);
-  blk_each_rc<NT, 4, cplx<T>>(
-      nn, k, [&](int i, int c) { return cvt<T>(vload(i, c)); },
-      [&](int i, int c, cplx<T> v) {
-        Vt[(size_t)i * k + c] = v;
-        site[(size_t)c * nn + i] = cj(v);
-      });
+  select_store<T, NT>(m, s, j, k, vload, Vt);
+  return k;
+}
+
+// The kept space when the relative cut alone decides (no chi_max or
+// physical bound binding): the k given columns from vload, and the discarded
+// fraction wgt of the trace into the fidelity.
+template <typename T, int NT, typename VF>
+__device__ int select_fixed(const MpsDev &m, int s, int j, int k, double wgt, VF vload, cplx<T> *Vt) {
   if (threadIdx.x == 0) {
-    bnd(m, s)[j] = k;
-    bnd(m, s)[j + 1] = w[j + 1];
+    m.fid[s] *= (1.0 - wgt);
+    auxp(m, s)[2] = k;
+    auxp(m, s)[3] = wbd(m, s)[j];
   }
-  __syncthreads();
+  select_store<T, NT>(m, s, j, k, vload, Vt);
   return k;
 }
 // The sorted eigenvalues in m.ev, the eigenvectors in V (ld nn).

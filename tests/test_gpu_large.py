@@ -78,17 +78,21 @@ def test_environment_path_doubled_bonds_to_256(B, prec):
     assert paths["env_steps"] > 0 and paths["qr_steps"] == 0 and paths["max_order"] == 256
 
 
-@pytest.mark.parametrize("prec,lds", [("fp32", 0), ("fp32", 64), ("fp64", 0)])
+@pytest.mark.parametrize("prec,lds", [("fp32", 32), ("fp32", 64), ("fp64", 0)])
 def test_environment_path_orders_to_128(B, prec, lds):
-    """Bonds reach 64 (chi_max 64 does not bind): eigen-solves of order
-    65..128 with rho in global scratch.  FP32: ranks up to 42 (LDS tile 32)
-    or 64 (tile 64) take the Gram of the Cholesky factor in LDS, larger ones
+    """Bonds reach 64 (chi_max 64 does not bind): truncations of order
+    65..128 with rho in global scratch.  FP32: where the relative cut alone
+    decides and its pivot count fits the LDS tile (42 with tile 32, 64 with
+    tile 64), the kept space is the orthonormalised leading rows of the
+    pivoted Cholesky factor; other cuts take the Gram of the factor in LDS or
     the one-sided Jacobi on the factor rows in global scratch."""
     circ = entangling_circuit(12, 20, 4, 7, meas_every=6)
     paths, ores = parity_large(B, circ, 64, prec, range(0, 4), (2, 256), lds=lds)
     assert max(max(o.bond_trace) for o in ores.values()) == 64
     assert paths["env_steps"] > 0 and paths["qr_steps"] == 0
     assert paths["eig_global"] > 0 and paths["max_order"] == 128
+    if prec == "fp32":
+        assert paths["cholqr"] > 0
 
 
 @pytest.mark.parametrize("prec,mode", [("fp32", (2, 256)), ("fp64", (2, 256)), ("fp32", (2, 128)),
@@ -117,3 +121,6 @@ def test_fp32_chi_binding_at_orders_above_64(B):
     paths, ores = parity_large(B, circ, 48, "fp32", range(0, 4), (2, 256))
     assert any(o.trunc_err > 0.1 for o in ores.values())
     assert paths["max_order"] == 96 and paths["eig_global"] > 0
+    # binding cuts need the eigenvalues: not all global-scratch cuts can take
+    # the Cholesky rows
+    assert paths["cholqr"] < paths["eig_global"] + paths["eig_global_gt128"]
