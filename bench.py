@@ -23,8 +23,10 @@ Prints one JSON line.  value = (shots x rotations per step x K) / time.
 roofline: the kernel class with the largest time in the timed region, its
 algorithmic work per step (counted on the device from the realised bond
 dimensions in a separate replay of one step: the counters slow the kernels
-they count) over its own launch time in the timed region (HIP events around
-each of its launches on the library stream).  graph: the same step captured
+they count; each truncation eigen-solve of order nn at a fixed 107/8 nn^3
+FP64 flops, whatever route ran) over its own launch time in the timed region
+(HIP events around each of its launches on the library stream); `executed`
+beside it recounts the solves at the flops they executed.  graph: the same step captured
 once as a HIP graph and replayed (time per replay, records bit-identical to
 the eager step).  plain_fp64: the plain per-shot FP64 GPU form (per-step
 kernels, one shot at a time) of the window on the first shots with the
@@ -445,13 +447,26 @@ def main():
             f64 = prof["layer_fp64_flops"]
             f32 = d["flops"] - f64
             peak = d["flops"] / (f32 / PEAKS["fp32_vector_TFs"] + f64 / PEAKS["fp64_vector_TFs"])
+        executed = None
+        if dom == "layer" and d["flops"] > 0:
+            # the same work with the eigen-solves at their executed flop count
+            # (route and sweeps as run) instead of the fixed nominal cost
+            dn = (paths.get("eig_nominal_flops", 0.0) - paths.get("eig_exec_flops", 0.0)) * K
+            fx = d["flops"] - dn
+            f64x = prof["layer_fp64_flops"] - dn
+            px = fx / ((fx - f64x) / PEAKS["fp32_vector_TFs"] + f64x / PEAKS["fp64_vector_TFs"])
+            ax = fx / (d["ms"] / 1e3) / 1e12
+            executed = {"flops_per_launch": fx / d["launches"], "achieved": ax, "peak": px, "frac": ax / px,
+                        "eigen_nominal_flops_per_launch": paths.get("eig_nominal_flops", 0.0) * K / d["launches"],
+                        "eigen_executed_flops_per_launch": paths.get("eig_exec_flops", 0.0) * K / d["launches"]}
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": measured_traffic(dom, args.window), "kernel_class": dom,
                 "launches": d["launches"], "avg_launch_ms": per_launch_ms,
                 "algorithmic_flops_per_launch": d["flops"] / d["launches"],
                 "fp64_flops_share": (prof["layer_fp64_flops"] / d["flops"]) if dom == "layer" and d["flops"] else None,
                 "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
-                "share_of_step_time": d["ms"] / ms if ms > 0 else None}
+                "share_of_step_time": d["ms"] / ms if ms > 0 else None,
+                "executed": executed}
     graph = None
     if not args.no_graph:
         del sim

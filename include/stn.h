@@ -288,7 +288,9 @@ enum { STN_K_TABLEAU = 0,  /* tableau gates, rewrite, frame change */
 stn_status stn_profile(stn_ctx *ctx, unsigned class_mask);
 
 /* Reads (and clears the event list of) the profile: per class the summed
- * kernel milliseconds, algorithmic flops and bytes, and the number of timed
+ * kernel milliseconds, algorithmic flops and bytes (each truncation
+ * eigen-solve of order nn counted at a fixed 107/8 nn^3 FP64 flops, whatever
+ * route ran; see stn_profile_paths for the executed count), and the number of timed
  * launches (arrays of STN_K_COUNT entries, any may be NULL), the total number
  * of eigen-solve sweeps executed (two-sided Jacobi sweeps on the FP64 path,
  * one-sided on the FP32 path), and the FP64 part (Gram + eigen-solve) of the
@@ -310,7 +312,7 @@ stn_status stn_profile_phases(stn_ctx *ctx, double *host_cycles);
 
 /* Branch counters of the fused layer kernel while profiling is on with
  * counters (stn_profile without STN_PROFILE_TIMING_ONLY), summed over shots
- * since the last stn_profile call; host_counts: 9 doubles, in order:
+ * since the last stn_profile call; host_counts: 11 doubles, in order:
  *  0 two-term steps whose left-to-right sweep formed left-environment Grams,
  *  1 steps that took the Householder QR sweep instead (a doubled bond of the
  *    span above the environment limit),
@@ -325,7 +327,12 @@ stn_status stn_profile_phases(stn_ctx *ctx, double *host_cycles);
  *    the Cholesky factor when its Gram does not fit the LDS tile),
  *  8 FP32-path truncations of rho in global scratch decided by the relative
  *    cut alone, whose kept space came from the orthonormalised leading rows
- *    of the pivoted Cholesky factor (no eigen-solve).
+ *    of the pivoted Cholesky factor (no eigen-solve),
+ *  9 the layer kernel's (and the per-step eigen kernel's) truncation solves
+ *    as counted by stn_profile_read: a fixed 107/8 nn^3 FP64 flops per
+ *    solve of order nn, whatever the route,
+ * 10 the flops those solves executed (Cholesky, the Jacobi sweeps actually
+ *    run, Cholesky QR, products).
  * Synchronises. */
 stn_status stn_profile_paths(stn_ctx *ctx, double *host_counts);
 

@@ -47,13 +47,13 @@ enum { K_TABLEAU = 0, K_BUILD, K_QR, K_GEMM, K_GRAM, K_EIGEN, K_SELECT, K_EXPECT
 // Device work counters: [K_COUNT][2] flops/bytes, Jacobi sweeps, layer FP64
 // flops, the fused kernel's per-phase cycle totals, then its branch counters
 // (kPath* below).
-constexpr int kPhaseBase = 2 * K_COUNT + 2, kPhases = 8, kPathBase = kPhaseBase + kPhases, kPaths = 9;
+constexpr int kPhaseBase = 2 * K_COUNT + 2, kPhases = 8, kPathBase = kPhaseBase + kPhases, kPaths = 11;
 constexpr int kWorkWords = kPathBase + kPaths;
 // Branch counters of the fused kernel (steps that took each route; the
 // largest eigen-solve order as an integer; cycles spent in the pivoted
 // Cholesky part of the FP32-path eigen-solve).
 enum { kPathEnv = 0, kPathQr, kPathEigLds, kPathEigGlobal, kPathEigGlobal129, kPathMaxOrder, kPathCholCycles,
-       kPathJacGlobal, kPathCholQr };
+       kPathJacGlobal, kPathCholQr, kPathEigNominal, kPathEigExec };
 // Largest doubled bond for which the fused kernel keeps the left-environment
 // Grams of a span (FP64 complex) instead of a QR sweep; the Grams of a span
 // are packed into a per-shot store of n x kEnvStore^2 elements (smaller when

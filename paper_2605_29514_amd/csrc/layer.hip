@@ -581,9 +581,16 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         }
       }
       if (tid == 0) {
-        const double f64 = gemm_flops(nn, nn, Lx) + fe;
+        // the solve is counted at its fixed nominal cost (eig_nominal_flops),
+        // whatever route and sweep count ran; the executed count is kept apart
+        const double fn = eig_nominal_flops(nn);
+        const double f64 = gemm_flops(nn, nn, Lx) + fn;
         add_work(m, cls, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
-        if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
+        if (f64c) {
+          atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work
+          atomicAdd(&m.work[kPathBase + kPathEigNominal], fn);
+          atomicAdd(&m.work[kPathBase + kPathEigExec], fe);
+        }
         if (m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)*sweeps);
         if (clk.on && t_chol) atomicAdd(&m.work[kPathBase + kPathCholCycles], (double)(t_chol - clk.t));
       }

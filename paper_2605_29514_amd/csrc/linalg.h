@@ -1193,6 +1193,11 @@ template <typename T> __device__ inline double eig_rot_tol() { return 1e-10; }
 // Pivoted-Cholesky cut: captures every eigenvalue above eps_cut tr G (the
 // truncation threshold), but not below a few roundings of tr G.
 __device__ inline double chol_tol(double eps_cut, int nn) { return fmax(eps_cut / (nn > 0 ? nn : 1), 4e-16); }
+// Algorithmic work of one truncation eigen-solve of order nn, whatever the
+// route: that of a dense Hermitian solve with vectors, 107 chi^3 FP64 flops
+// at the saturated order nn = 2 chi (107/8 nn^3), fixed so that the counted
+// work of a step does not depend on sweep counts or on the route taken.
+__device__ inline double eig_nominal_flops(int nn) { return 107.0 / 8.0 * nn * nn * (double)nn; }
 
 // ------------------------------------------------------------ truncation
 // Keep k' = min(chi_max, #{lambda_i > eps sum lambda}, 2^min(j, n-j)) largest

@@ -235,7 +235,13 @@ __global__ void k_eig(MpsDev m, int j) {
                      chol_tol(m.eps_cut, nn), eig_conv_tol<T>(), eig_rot_tol<T>());
   }
   // work: the method's operation count; bytes: read G, write eigenvalues and vectors
-  if (threadIdx.x == 0) add_work(m, K_EIGEN, fe, 16.0 * 2 * nn * nn + 8.0 * nn);
+  if (threadIdx.x == 0) {
+    add_work(m, K_EIGEN, eig_nominal_flops(nn), 16.0 * 2 * nn * nn + 8.0 * nn);
+    if (m.prof) {
+      atomicAdd(&m.work[kPathBase + kPathEigNominal], eig_nominal_flops(nn));
+      atomicAdd(&m.work[kPathBase + kPathEigExec], fe);
+    }
+  }
   if (threadIdx.x == 0 && m.prof) atomicAdd(&m.work[2 * K_COUNT], (double)sweeps);
 }
 

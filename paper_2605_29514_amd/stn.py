@@ -407,10 +407,10 @@ class Simulator:
 
     def profile_paths(self) -> dict:
         """Fused-kernel branch counters (see stn_profile_paths)."""
-        out = np.zeros(9, np.float64)
+        out = np.zeros(11, np.float64)
         self._check(self.lib.stn_profile_paths(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
         names = ["env_steps", "qr_steps", "eig_lds", "eig_global", "eig_global_gt128", "max_order",
-                 "chol_cycles", "jacobi_global", "cholqr"]
+                 "chol_cycles", "jacobi_global", "cholqr", "eig_nominal_flops", "eig_exec_flops"]
         return dict(zip(names, out.tolist()))
 
     def set_layer_mode(self, mode: int):
