@@ -399,12 +399,25 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         gemm_direct<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, F, Dr, 0, Ej, Dr);
         __syncthreads();
       } else {
-        blk_gemm<double, T, double, double, NT>(Dl, 2 * Dr, Dl, Ep, Dl, 0, wslot<T>(m, j, s), 2 * Dr, 0, F, 2 * Dr, lds);
-        blk_gemm<T, double, double, double, NT>(Dr, Dr, 2 * Dl, wslot<T>(m, j, s), Dr, 1, F, Dr, 0, Ej, Dr, lds);
+        // a middle site's block is block-diagonal in the two terms (rows
+        // a < dl and columns c < dr carry the first, the rest the second),
+        // so both products run per term on the nonzero blocks: half the work
+        const int dl = Dl / 2, dr = Dr / 2;
+        const cplx<T> *Bj = wslot<T>(m, j, s);
+        for (int t = 0; t < 2; ++t)
+          for (int p = 0; p < 2; ++p)   // F[:, p, c in t] = E[:, a in t] B[a in t, p, c in t]
+            blk_gemm<double, T, double, double, NT>(Dl, dr, dl, Ep + t * dl, Dl, 0,
+                                                    Bj + (size_t)t * dl * 2 * Dr + p * Dr + t * dr, 2 * Dr, 0,
+                                                    F + p * Dr + t * dr, 2 * Dr, lds);
+        for (int t = 0; t < 2; ++t)     // E_j[c in t, :] = B[(a in t, p), c in t]^H F[(a in t, p), :]
+          blk_gemm<T, double, double, double, NT>(dr, Dr, 2 * dl, Bj + (size_t)t * 2 * dl * Dr + t * dr, Dr, 1,
+                                                  F + (size_t)t * 2 * dl * Dr, Dr, 0, Ej + (size_t)t * dr * Dr, Dr,
+                                                  lds);
       }
       if (tid == 0) {
-        const double f = gemm_flops(Dl, 2 * Dr, Dl) + gemm_flops(Dr, Dr, 2 * Dl);
-        add_work(m, cls, f, (double)sizeof(cplx<T>) * 2 * Dl * Dr + 16.0 * (Dl * Dl + 2.0 * Dl * Dr + Dr * Dr));
+        // the nonzero blocks' work (half of the dense products)
+        const double f = 0.5 * (gemm_flops(Dl, 2 * Dr, Dl) + gemm_flops(Dr, Dr, 2 * Dl));
+        add_work(m, cls, f, (double)sizeof(cplx<T>) * Dl * Dr + 16.0 * (Dl * Dl + 2.0 * Dl * Dr + Dr * Dr));
         if (f64c) atomicAdd(&m.work[2 * K_COUNT + 1], f);
       }
     }
