@@ -1058,52 +1058,95 @@ __device__ bool chol_lower(int r, c64 *K, int ldk) {
 }
 
 // Inverse of a lower-triangular r x r matrix L in place (ld ldk, real
-// positive diagonal, zero upper triangle), row by row: row i of the inverse
-// W is W_ii = 1 / L_ii, W_ij = -(sum_{k=j}^{i-1} L_ik W_kj) / L_ii (j < i),
-// from the rows above (already inverted) and row i of L; row: r complex.
+// positive diagonal, zero upper triangle), row by row with one barrier per
+// row: row i of the inverse W is W_ii = 1 / L_ii,
+// W_ij = -(sum_{k=j}^{i-1} L_ik W_kj) / L_ii (j < i), from row i of L and
+// the rows above, of which row i-1 is still in its staging buffer while it
+// is written back (no thread reads L's row i-1 after step i-1).
+// stage: 2 r complex.
 template <int NT>
-__device__ void trinv_lower(int r, c64 *K, int ldk, c64 *row) {
+__device__ void trinv_lower(int r, c64 *K, int ldk, c64 *stage) {
   const int tid = threadIdx.x;
   for (int i = 0; i < r; ++i) {
+    const c64 *prev = stage + ((i + 1) & 1) * r;      // W row i - 1
+    c64 *cur = stage + (i & 1) * r;
     const double il = 1.0 / K[(size_t)i * ldk + i].x;
     for (int j = tid; j <= i; j += NT) {
       if (j == i) {
-        row[j] = mk<double>(il, 0);
+        cur[j] = mk<double>(il, 0);
       } else {
-        c64 acc = mk<double>(0, 0);
-        for (int k = j; k < i; ++k) acc = acc + K[(size_t)i * ldk + k] * K[(size_t)k * ldk + j];
-        row[j] = (-il) * acc;
+        c64 acc = K[(size_t)i * ldk + (i - 1)] * prev[j];
+        for (int k = j; k < i - 1; ++k) acc = acc + K[(size_t)i * ldk + k] * K[(size_t)k * ldk + j];
+        cur[j] = (-il) * acc;
       }
     }
-    __syncthreads();
-    for (int j = tid; j <= i; j += NT) K[(size_t)i * ldk + j] = row[j];
+    if (i > 0)
+      for (int j = tid; j < i; j += NT) K[(size_t)(i - 1) * ldk + j] = prev[j];
     __syncthreads();
   }
+  if (r > 0)
+    for (int j = tid; j < r; j += NT) K[(size_t)(r - 1) * ldk + j] = stage[((r - 1) & 1) * r + j];
+  __syncthreads();
 }
 
 // Orthonormal rows spanning the r rows of R (r x nn, ld ldr, FP64), in
-// place, by two passes of Cholesky QR: K = R R^H = L L^H, R <- L^{-1} R.  A
-// pass leaves a loss of orthogonality of about eps_64 cond(R)^2, which the
-// second pass (on rows already orthogonal to that level) removes; the rows
-// here come from a pivoted Cholesky stopped at a relative pivot of 1e-12
-// or more, so cond(R) stays far below the 1e8 at which that would fail.
-// K: r x r (ld ldk), row: r complex, Tmp: r x nn (ld ldr).  Returns false
-// when a factorisation meets a non-positive pivot; R then holds its input.
+// place.  First pass, Cholesky QR: K = R R^H = L L^H, Q = L^{-1} R; it leaves
+// a loss of orthogonality E = Q Q^H - I of about eps_64 cond(R)^2 (the rows
+// here come from a pivoted Cholesky stopped at a relative pivot of 1e-12 or
+// more, so cond(R) stays near 1e6 and |E| near 1e-4).  Second pass, the
+// inverse square root of Q Q^H = I + E to second order:
+// R <- (I - E/2 + 3 E^2 / 8) Q, exact to O(|E|^3); when max |E_ij| passes
+// 1e-3 a second Cholesky QR pass runs instead.  K: (r + 1)(r + 2) complex
+// (ld r + 1; the Gram, its factor and inverse, then staging rows), Tmp:
+// r x nn (ld ldr).  Returns false when a factorisation meets a
+// non-positive pivot; R then holds its input.
 template <int NT>
-__device__ __noinline__ bool orth_rows(int r, int nn, c64 *R, int ldr, c64 *Tmp, c64 *K, int ldk, c64 *row,
-                                      double *flops) {
-  for (int pass = 0; pass < 2; ++pass) {
-    const c64 *src = pass ? Tmp : R;
-    c64 *dst = pass ? R : Tmp;
-    gemm_direct<double, double, double, double, NT>(r, r, nn, src, ldr, 0, src, ldr, 1, K, ldk);
-    __syncthreads();
-    if (!chol_lower<NT>(r, K, ldk)) return false;
-    trinv_lower<NT>(r, K, ldk, row);
-    gemm_direct<double, double, double, double, NT>(r, nn, r, K, ldk, 0, src, ldr, 0, dst, ldr);
-    __syncthreads();
-    // K and the product (8 r^2 nn each), factor and inverse (8 r^3 / 6 each)
-    *flops += 2 * gemm_flops(r, r, nn) + 8.0 * r * r * (double)r / 3.0;
+__device__ __noinline__ bool orth_rows(int r, int nn, c64 *R, int ldr, c64 *Tmp, c64 *K, double *flops) {
+  const int ldk = r + 1, tid = threadIdx.x;
+  c64 *stage = K + (size_t)r * ldk;
+  // pass 1: Tmp = L^{-1} R
+  gemm_direct<double, double, double, double, NT>(r, r, nn, R, ldr, 0, R, ldr, 1, K, ldk);
+  __syncthreads();
+  if (!chol_lower<NT>(r, K, ldk)) return false;
+  trinv_lower<NT>(r, K, ldk, stage);
+  gemm_direct<double, double, double, double, NT>(r, nn, r, K, ldk, 0, R, ldr, 0, Tmp, ldr);
+  __syncthreads();
+  *flops += 2 * gemm_flops(r, r, nn) + 8.0 * r * r * (double)r / 3.0;
+  // pass 2: E = Tmp Tmp^H - I (in K), E^2 (in R, free now)
+  gemm_direct<double, double, double, double, NT>(r, r, nn, Tmp, ldr, 0, Tmp, ldr, 1, K, ldk);
+  __syncthreads();
+  double mx = 0;
+  for (int e = tid; e < r * r; e += NT) {
+    const int i = e / r, j = e - (e / r) * r;
+    c64 v = K[(size_t)i * ldk + j];
+    if (i == j) v.x -= 1.0;
+    K[(size_t)i * ldk + j] = v;
+    mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
   }
+  mx = bmax<NT>(mx);
+  if (mx <= 1e-3) {
+    gemm_direct<double, double, double, double, NT>(r, r, r, K, ldk, 0, K, ldk, 0, R, ldr);
+    __syncthreads();
+    for (int e = tid; e < r * r; e += NT) {
+      const int i = e / r, j = e - (e / r) * r;
+      c64 c = -0.5 * K[(size_t)i * ldk + j] + 0.375 * R[(size_t)i * ldr + j];
+      if (i == j) c.x += 1.0;
+      K[(size_t)i * ldk + j] = c;
+    }
+    __syncthreads();
+    gemm_direct<double, double, double, double, NT>(r, nn, r, K, ldk, 0, Tmp, ldr, 0, R, ldr);
+    __syncthreads();
+    *flops += 2 * gemm_flops(r, r, nn) + gemm_flops(r, r, r);
+    return true;
+  }
+  // large loss of orthogonality: a second Cholesky QR pass, Tmp -> R
+  for (int e = tid; e < r; e += NT) K[(size_t)e * ldk + e].x += 1.0;   // back to Tmp Tmp^H
+  __syncthreads();
+  if (!chol_lower<NT>(r, K, ldk)) return false;
+  trinv_lower<NT>(r, K, ldk, stage);
+  gemm_direct<double, double, double, double, NT>(r, nn, r, K, ldk, 0, Tmp, ldr, 0, R, ldr);
+  __syncthreads();
+  *flops += 2 * gemm_flops(r, r, nn) + 8.0 * r * r * (double)r / 3.0;
   return true;
 }
 
