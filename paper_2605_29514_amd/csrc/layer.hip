@@ -123,16 +123,17 @@ __device__ inline Fallback fallback(const MpsDev &m, int s) {
 
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void blk_gemm(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
-                         const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, char *lds) {
+                         const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, char *lds, int lower = 0) {
   // 512 threads: eight waves each take their own 16 x 32 output blocks
-  // straight from memory (the LDS-staged tile is shaped for up to four)
+  // straight from memory (the LDS-staged tile is shaped for up to four);
+  // lower: output blocks wholly above the diagonal are skipped
   if constexpr (NT >= 512) {
-    gemm_direct<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc);
+    gemm_direct<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, lower);
   } else {
     if (M <= kDirectGemm && N <= kDirectGemm && K <= kDirectGemm)
-      gemm_direct<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc);
+      gemm_direct<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, lower);
     else
-      gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds + u_off(NT));
+      gemm_tiles<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, 0, 1, lds + u_off(NT), lower);
   }
   __syncthreads();
 }
@@ -467,7 +468,9 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         gemm_direct<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, F, nn, 0, Gl, nn + 1);
         __syncthreads();
       } else {
-        blk_gemm<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, Fs, nn, 0, Gg, nn, lds);
+        // FP32 path: rho only feeds the left-looking Cholesky, which reads
+        // its lower triangle
+        blk_gemm<T, double, double, double, NT>(nn, nn, Lx, X, nn, 1, Fs, nn, 0, Gg, nn, lds, sizeof(T) == 4);
       }
       if (tid == 0) {
         add_work(m, cls, gemm_flops(Lx, nn, Lx), 16.0 * (Lx * Lx + Lx * nn));
@@ -477,7 +480,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
       gemm_direct<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gl, nn + 1);
       __syncthreads();
     } else {
-      blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds);
+      blk_gemm<T, T, double, double, NT>(nn, nn, Lx, X, nn, 1, X, nn, 0, Gg, nn, lds, sizeof(T) == 4);
     }
     clk.lap(m, 5);
     const c64 *Vsel = m.V + s * m.V_cap;     // sorted eigenvectors, nn x nn (not in LDS steps)
@@ -546,7 +549,7 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
           double tr, resid;
           int rc;
           c64 *wpl = reinterpret_cast<c64 *>(lds + kWp);
-          rk = chol_rows<NT>(nn, Gg, nn, Rs, nn, ct, f.dg, f.pos, wpl, m.err, &tr, &fe, m.eps_cut, &rc, &resid);
+          rk = chol_rows<NT>(nn, Gg, nn, Rs, nn, ct, f.dg, f.pos, wpl, m.err, &tr, &fe, m.eps_cut, &rc, &resid, true);
           if (clk.on && tid == 0) t_chol = clock64();
           const int kt = eig_n > 32 ? k_gram_order(64) : k_gram_order(32);
           const int eb = j < m.n - j ? j : m.n - j;
@@ -597,7 +600,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
         // the solve is counted at its fixed nominal cost (eig_nominal_flops),
         // whatever route and sweep count ran; the executed count is kept apart
         const double fn = eig_nominal_flops(nn);
-        const double f64 = gemm_flops(nn, nn, Lx) + fn;
+        // rho = X^H (E X) is Hermitian: its algorithmic work is one triangle
+        const double f64 = 4.0 * Lx * nn * (nn + 1.0) + fn;
         add_work(m, cls, f64, (double)sizeof(cplx<T>) * Lx * nn + 16.0 * 3 * nn * nn + 8.0 * nn);
         if (f64c) {
           atomicAdd(&m.work[2 * K_COUNT + 1], f64);        // FP64 share of the layer work

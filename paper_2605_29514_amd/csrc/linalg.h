@@ -260,7 +260,7 @@ __device__ void gemm_tile(int M, int N, int K, const cplx<TA> *A, int lda, int o
 // 16 k.  The k order of the accumulation is that of gemm_tile.
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void gemm_direct(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
-                            const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc) {
+                            const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, int lower = 0) {
   using MF = Mfma<ACC>;
   using V = typename MF::V;
   constexpr int NW = NT / 64, KC = 16;
@@ -269,6 +269,7 @@ __device__ void gemm_direct(int M, int N, int K, const cplx<TA> *A, int lda, int
   const int nbm = (M + 15) / 16, nbp = (N + 31) / 32;
   for (int bp = wave; bp < nbm * nbp; bp += NW) {
     const int m0 = (bp / nbp) * 16, n0 = (bp % nbp) * 32;
+    if (lower && m0 + 16 <= n0) continue;     // lower: blocks wholly above the diagonal are skipped
     const int m = m0 + r16, n1 = n0 + r16, n2 = n0 + 16 + r16;
     V re[2], im[2];
 #pragma unroll
@@ -323,11 +324,12 @@ __device__ void gemm_direct(int M, int N, int K, const cplx<TA> *A, int lda, int
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void gemm_tiles(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
                            const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, int t0,
-                           int dt, void *stage) {
+                           int dt, void *stage, int lower = 0) {
   constexpr int TM = MTile<NT>::TM, TN = MTile<NT>::TN;
   const int ntm = (M + TM - 1) / TM, ntn = (N + TN - 1) / TN;
   for (int t = t0; t < ntm * ntn; t += dt)
-    gemm_tile<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, t / ntn, t % ntn, stage);
+    if (!lower || (t / ntn + 1) * TM > (t % ntn) * TN)
+      gemm_tile<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, t / ntn, t % ntn, stage);
 }
 
 // ----------------------------------------------------- Householder QR
@@ -924,7 +926,8 @@ __device__ double jac_rows(int nn, int r, c64 *G, int ld, double *ev, c64 *Vout,
 // pivot order, with R^H R = A up to the part left out; the Schur diagonal
 // follows each row (d_q -= |R_k[q]|^2).  Stops once d <= chol_tol tr A (the
 // eigenvalues left out are then at most nn chol_tol tr A in total), returns
-// the rank r and (to every thread) tr A in *trace.  The pivots d never grow
+// the rank r and (to every thread) tr A in *trace.  lower: only A's lower
+// triangle is read (A_pj = conj(A_jp) above the diagonal).  The pivots d never grow
 // from step to step; *r_cut is the number of steps taken while d was above
 // cut_tol tr A (cut_tol >= chol_tol) and *resid the trace of the Schur
 // complement left at that point (tr A minus the squared norms of those rows).
@@ -932,7 +935,7 @@ __device__ double jac_rows(int nn, int r, c64 *G, int ld, double *ev, c64 *Vout,
 template <int NT>
 __device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double chol_tol, double *dg, int *pos,
                          c64 *wp, int *err, double *trace, double *flops, double cut_tol, int *r_cut,
-                         double *resid) {
+                         double *resid, bool lower = false) {
   const int tid = threadIdx.x;
   constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
   __shared__ double amv[2 * NW];
@@ -997,7 +1000,7 @@ __device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double 
         c64 val;
         if (j == p) val = mk<double>(sqrt(d), 0);
         else if (!live) val = mk<double>(0, 0);
-        else val = isd * (A[(size_t)p * lda + j] - acc);
+        else val = isd * ((lower && j > p ? cj(A[(size_t)j * lda + p]) : A[(size_t)p * lda + j]) - acc);
         R[(size_t)k * ldr + j] = val;
       }
       if (G > 1) __syncthreads();
