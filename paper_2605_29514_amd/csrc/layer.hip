@@ -549,7 +549,11 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
           double tr, resid;
           int rc;
           c64 *wpl = reinterpret_cast<c64 *>(lds + kWp);
-          rk = chol_rows<NT>(nn, Gg, nn, Rs, nn, ct, f.dg, f.pos, wpl, m.err, &tr, &fe, m.eps_cut, &rc, &resid, true);
+          // the first factor rows also in the LDS tile (free until the Gram of
+          // the factor is formed there)
+          const int tl = (int)((lds_bytes(NT, false, eig_n) - u_off(NT)) / ((size_t)nn * sizeof(c64)));
+          rk = chol_rows<NT>(nn, Gg, nn, Rs, nn, ct, f.dg, f.pos, wpl, m.err, &tr, &fe, m.eps_cut, &rc, &resid, true,
+                             Gl, tl);
           if (clk.on && tid == 0) t_chol = clock64();
           const int kt = eig_n > 32 ? k_gram_order(64) : k_gram_order(32);
           const int eb = j < m.n - j ? j : m.n - j;

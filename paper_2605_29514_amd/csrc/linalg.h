@@ -927,15 +927,18 @@ __device__ double jac_rows(int nn, int r, c64 *G, int ld, double *ev, c64 *Vout,
 // follows each row (d_q -= |R_k[q]|^2).  Stops once d <= chol_tol tr A (the
 // eigenvalues left out are then at most nn chol_tol tr A in total), returns
 // the rank r and (to every thread) tr A in *trace.  lower: only A's lower
-// triangle is read (A_pj = conj(A_jp) above the diagonal).  The pivots d never grow
+// triangle is read (A_pj = conj(A_jp) above the diagonal).  Rl: LDS room
+// for the first tl rows (ld nn), which every later step re-reads: they are
+// kept there as well as in R.  The pivots d never grow
 // from step to step; *r_cut is the number of steps taken while d was above
 // cut_tol tr A (cut_tol >= chol_tol) and *resid the trace of the Schur
 // complement left at that point (tr A minus the squared norms of those rows).
 // Scratch: dg (nn doubles), pos (nn ints), wp (NT complex doubles).
 template <int NT>
-__device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double chol_tol, double *dg, int *pos,
+__device__ __noinline__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double chol_tol, double *dg,
+                                      int *pos,
                          c64 *wp, int *err, double *trace, double *flops, double cut_tol, int *r_cut,
-                         double *resid, bool lower = false) {
+                         double *resid, bool lower = false, c64 *Rl = nullptr, int tl = 0) {
   const int tid = threadIdx.x;
   constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
   __shared__ double amv[2 * NW];
@@ -983,7 +986,11 @@ __device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double 
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int t = t0 + u * G;
-            if (t < k) { rp[u] = R[(size_t)t * ldr + p]; rj[u] = R[(size_t)t * ldr + j]; }
+            if (t < k) {
+              const c64 *row = t < tl ? Rl + (size_t)t * nn : R + (size_t)t * ldr;
+              rp[u] = row[p];
+              rj[u] = row[j];
+            }
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
@@ -1002,6 +1009,7 @@ __device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double 
         else if (!live) val = mk<double>(0, 0);
         else val = isd * ((lower && j > p ? cj(A[(size_t)j * lda + p]) : A[(size_t)p * lda + j]) - acc);
         R[(size_t)k * ldr + j] = val;
+        if (k < tl) Rl[(size_t)k * nn + j] = val;
       }
       if (G > 1) __syncthreads();
     }
@@ -1012,7 +1020,7 @@ __device__ int chol_rows(int nn, const c64 *A, int lda, c64 *R, int ldr, double 
     vi = 0x7fffffff;
     for (int q = tid; q < nn; q += NT) {
       if (q == p || pos[q] < nn) continue;
-      const double nd = dg[q] - norm2(R[(size_t)k * ldr + q]);
+      const double nd = dg[q] - norm2(k < tl ? Rl[(size_t)k * nn + q] : R[(size_t)k * ldr + q]);
       dg[q] = nd;
       if (nd > v) { v = nd; vi = q; }
     }
