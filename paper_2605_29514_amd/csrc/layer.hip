@@ -167,15 +167,39 @@ __device__ void blk_qr(c64 *gvs, double *gvd, int rows, int cols, cplx<T> *A, cp
   }
 }
 
+// FP32 path: the Q of a centre move by Cholesky QR (qr_cols_cq, its Gram in
+// the LDS tile) when the tile holds it, then R = Q^H X from the stored Q;
+// false when it does not apply or declines (the Householder QR runs then).
+template <typename T, int NT>
+__device__ bool move_cq(const MpsDev &m, int s, int rows, int cols, const cplx<T> *X, cplx<T> *Qd, int qt,
+                        cplx<T> *R, char *lds, int eig_n) {
+  if constexpr (sizeof(T) == 4) {
+    if (cols > rows || cols > (eig_n > 32 ? k_gram_order(64) : k_gram_order(32))) return false;
+    c64 *K = reinterpret_cast<c64 *>(lds + u_off(NT));
+    if (!qr_cols_cq<NT>(rows, cols, X, Qd, qt, K, m.G + s * m.G_cap, m.V + s * m.V_cap)) return false;
+    // FP64 accumulation: R carries the small singular directions of X,
+    // whose relative accuracy an FP32 sum over the rows would lose
+    if (qt)
+      gemm_direct<T, T, T, double, NT>(cols, cols, rows, Qd, rows, 0, X, cols, 0, R, cols);
+    else
+      gemm_direct<T, T, T, double, NT>(cols, cols, rows, Qd, cols, 1, X, cols, 0, R, cols);
+    __syncthreads();
+    return true;
+  } else {
+    return false;
+  }
+}
+
 // Centre move c -> c+1 (QR of A_c, R into A_{c+1}).
 template <typename T, int NT>
-__device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds, int cls) {
+__device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds, int cls, int eig_n) {
   int *b = bnd(m, s);
   const int rows = 2 * b[c], cols = b[c + 1], N = 2 * b[c + 2];
   const int p = rows < cols ? rows : cols;
   cplx<T> *X = scr<T>(m.T, m.T_cap, s), *R = scr<T>(m.R, m.R_cap, s);
   blk_copy<T, NT>(X, slot<T>(m, c, s), rows * cols);
-  blk_qr<T, NT>(fallback(m, s).vs, fallback(m, s).vd, rows, cols, X, slot<T>(m, c, s), 0, R, lds);
+  if (!move_cq<T, NT>(m, s, rows, cols, X, slot<T>(m, c, s), 0, R, lds, eig_n))
+    blk_qr<T, NT>(fallback(m, s).vs, fallback(m, s).vd, rows, cols, X, slot<T>(m, c, s), 0, R, lds);
   blk_gemm<T, T, T, T, NT>(p, N, cols, R, cols, 0, slot<T>(m, c + 1, s), N, 0, X, N, lds);
   if (threadIdx.x == 0) {
     b[c + 1] = p;
@@ -188,7 +212,7 @@ __device__ void blk_move_right(const MpsDev &m, int s, int c, char *lds, int cls
 
 // Centre move c -> c-1 (LQ of A_c via the QR of A_c^H, L into A_{c-1}).
 template <typename T, int NT>
-__device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds, int cls) {
+__device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds, int cls, int eig_n) {
   int *b = bnd(m, s);
   const int dl = b[c], dr = b[c + 1], M = 2 * b[c - 1];
   const int rows = 2 * dr, cols = dl, p = rows < cols ? rows : cols;
@@ -199,7 +223,8 @@ __device__ void blk_move_left(const MpsDev &m, int s, int c, char *lds, int cls)
     X[(size_t)cc * dl + a] = cj(A[e]);
   }
   __syncthreads();
-  blk_qr<T, NT>(fallback(m, s).vs, fallback(m, s).vd, rows, cols, X, slot<T>(m, c, s), 1, R, lds);
+  if (!move_cq<T, NT>(m, s, rows, cols, X, slot<T>(m, c, s), 1, R, lds, eig_n))
+    blk_qr<T, NT>(fallback(m, s).vs, fallback(m, s).vd, rows, cols, X, slot<T>(m, c, s), 1, R, lds);
   blk_gemm<T, T, T, T, NT>(M, p, cols, slot<T>(m, c - 1, s), cols, 0, R, cols, 1, X, p, lds);
   if (threadIdx.x == 0) {
     b[c] = p;
@@ -258,8 +283,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
   int *b = bnd(m, s), *w = wbd(m, s);
   if (l == r) {
     if (!unitary) {
-      while (c < l) { blk_move_right<T, NT>(m, s, c, lds, cls); ++c; }
-      while (c > l) { blk_move_left<T, NT>(m, s, c, lds, cls); --c; }
+      while (c < l) { blk_move_right<T, NT>(m, s, c, lds, cls, eig_n); ++c; }
+      while (c > l) { blk_move_left<T, NT>(m, s, c, lds, cls, eig_n); --c; }
     }
     c64 o1[4], o2[4];
     so.get(l, o1, o2);
@@ -290,8 +315,8 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
     return;
   }
   clk.lap(m, 0);
-  while (c < l) { blk_move_right<T, NT>(m, s, c, lds, cls); ++c; }
-  while (c > r) { blk_move_left<T, NT>(m, s, c, lds, cls); --c; }
+  while (c < l) { blk_move_right<T, NT>(m, s, c, lds, cls, eig_n); ++c; }
+  while (c > r) { blk_move_left<T, NT>(m, s, c, lds, cls, eig_n); --c; }
   clk.lap(m, 1);
   // Environment path: when every doubled bond of the span fits the shot's
   // Gram store, the left-to-right sweep forms the left-environment Grams
@@ -706,8 +731,8 @@ __global__ void __launch_bounds__(NT, 2) k_meas(MpsDev m, const uint64_t *snap_s
   const int l = a.l, r = a.r;
   int c = a.center_in;
   PhaseClock clk(false);
-  while (c < l) { blk_move_right<T, NT>(m, s, c, lds, K_EXPECT); ++c; }
-  while (c > l) { blk_move_left<T, NT>(m, s, c, lds, K_EXPECT); --c; }
+  while (c < l) { blk_move_right<T, NT>(m, s, c, lds, K_EXPECT, eig_n); ++c; }
+  while (c > l) { blk_move_left<T, NT>(m, s, c, lds, K_EXPECT, eig_n); --c; }
   // centre norm and <phi|P'|phi>
   double part = 0;
   {

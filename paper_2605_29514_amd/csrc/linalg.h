@@ -1161,6 +1161,54 @@ __device__ __noinline__ bool orth_rows(int r, int nn, c64 *R, int ldr, c64 *Tmp,
   return true;
 }
 
+// Orthonormal columns spanning the cols columns of the FP32 matrix X (rows x
+// cols, row-major, rows >= cols, full column rank): Cholesky QR in FP64,
+// K = X^H X = L L^H, Q1 = X L^{-H}, then the second-order inverse square root
+// of Q1^H Q1 = I + E: Q = Q1 (I - E/2 + 3 E^2 / 8).  Q goes to Qd in FP32, as
+// Q (qt = 0, rows x cols) or Q^H (qt = 1, cols x rows).  K: (cols + 1)(cols
+// + 2) complex (ld cols + 1; LDS), G1: rows x cols, G2: cols x cols (FP64
+// scratch).  Returns false, Qd untouched, when the Gram is not positive
+// definite or E passes 1e-3 anywhere (X too ill-conditioned: the caller
+// falls back to Householder QR).
+template <int NT>
+__device__ __noinline__ bool qr_cols_cq(int rows, int cols, const cplx<float> *X, cplx<float> *Qd, int qt, c64 *K,
+                                        c64 *G1, c64 *G2) {
+  const int ldk = cols + 1, tid = threadIdx.x;
+  gemm_direct<float, float, double, double, NT>(cols, cols, rows, X, cols, 1, X, cols, 0, K, ldk);
+  __syncthreads();
+  if (!chol_lower<NT>(cols, K, ldk)) return false;
+  trinv_lower<NT>(cols, K, ldk, K + (size_t)cols * ldk);
+  gemm_direct<float, double, double, double, NT>(rows, cols, cols, X, cols, 0, K, ldk, 1, G1, cols);
+  __syncthreads();
+  gemm_direct<double, double, double, double, NT>(cols, cols, rows, G1, cols, 1, G1, cols, 0, K, ldk);
+  __syncthreads();
+  double mx = 0;
+  for (int e = tid; e < cols * cols; e += NT) {
+    const int i = e / cols, j = e - (e / cols) * cols;
+    c64 v = K[(size_t)i * ldk + j];
+    if (i == j) v.x -= 1.0;
+    K[(size_t)i * ldk + j] = v;
+    mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+  }
+  mx = bmax<NT>(mx);
+  if (!(mx <= 1e-3)) return false;
+  gemm_direct<double, double, double, double, NT>(cols, cols, cols, K, ldk, 0, K, ldk, 0, G2, cols);
+  __syncthreads();
+  for (int e = tid; e < cols * cols; e += NT) {
+    const int i = e / cols, j = e - (e / cols) * cols;
+    c64 c = -0.5 * K[(size_t)i * ldk + j] + 0.375 * G2[(size_t)i * cols + j];
+    if (i == j) c.x += 1.0;
+    K[(size_t)i * ldk + j] = c;
+  }
+  __syncthreads();
+  if (qt)   // Q^H = C^H Q1^H (C is Hermitian)
+    gemm_direct<double, double, float, double, NT>(cols, rows, cols, K, ldk, 1, G1, cols, 1, Qd, rows);
+  else
+    gemm_direct<double, double, float, double, NT>(rows, cols, cols, G1, cols, 0, K, ldk, 0, Qd, cols);
+  __syncthreads();
+  return true;
+}
+
 template <int NT>
 __device__ double eig_psd(int nn, c64 *G, int ld, double *ev, c64 *Vout, int *err, int *piv, int *pos,
                           double *dg, int *sweeps_out, double chol_tol, double conv_tol, double rot_tol,
