@@ -119,14 +119,16 @@ def window_stop(ops, window):
     rounds = split_rounds(ops)
     if window == "round1":
         return rounds[0][1]
-    if window == "r2l1":
+    if window in ("r2l1", "r2l2"):
         r2 = rounds[1][0]
-        return next(i for i in range(r2, len(ops)) if ops[i][0] == "rotate") + 1
+        rot = [i for i in range(r2, rounds[1][1]) if ops[i][0] == "rotate"]
+        return rot[0 if window == "r2l1" else 1] + 1
     raise ValueError(window)
 
 
 WINDOW_TEXT = {
     "r2l1": "syndrome round 1 + round 2 through its first crosstalk layer",
+    "r2l2": "syndrome round 1 + round 2 through its second crosstalk layer",
     "round1": "syndrome round 1",
 }
 

@@ -216,6 +216,17 @@ def test_d5_first_round_fp32(B, mode):
     run_parity(B, circ, 256, "fp32", range(4), mode=mode)
 
 
+def test_d5_chi32_two_rounds_fp32_binding(B):
+    """The d=5 NNN workload at chi_max = 32 over two syndrome rounds: chi binds
+    from round 2 on (about 2% of the weight is cut per shot).  Every shot is
+    compared with the oracle at its own bar from the summed cut sensitivity
+    (R14: about 9.5e-4 here), on the fused schedule the bench autotunes to."""
+    circ = W.memory_circuit(5, 2, 4, seed=21, theta_law="per_coupling", nnn=True, theta_range=(0.02, 0.10),
+                            p=1e-3)
+    g, ores, worst = run_parity(B, circ, 32, "fp32", range(4), mode=(2, 256))
+    assert all(o.trunc_err > 1e-3 for o in ores.values())
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_per_shot_theta(B, mode):
     circ = W.memory_circuit(3, 2, 6, seed=31, theta_law="per_shot", theta_range=(0.01, 0.08), nnn=True)
