@@ -583,7 +583,9 @@ __device__ void shot_step(const MpsDev &m, int s, int l, int r, const SiteOps &s
           const int kt = eig_n > 32 ? k_gram_order(64) : k_gram_order(32);
           const int eb = j < m.n - j ? j : m.n - j;
           const int kcap = eb < 30 && (1 << eb) < m.chi ? (1 << eb) : m.chi;
-          if (rc >= 1 && rc <= kcap && rc <= kt && orth_rows<NT>(rc, nn, Rs, nn, V, Gl, &fe)) {
+          // the Gram of the kept rows in LDS when it fits, else in the shot's
+          // rho scratch (rho is dead once factored)
+          if (rc >= 1 && rc <= kcap && orth_rows<NT>(rc, nn, Rs, nn, V, rc <= kt ? Gl : Gg, &fe)) {
             qk = rc;
             qw = tr > 0 ? resid / tr : 0.0;
             if (m.prof && tid == 0) atomicAdd(&m.work[kPathBase + kPathCholQr], 1.0);

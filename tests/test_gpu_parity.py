@@ -8,6 +8,8 @@ up to a global phase (fidelity) when the frames agree.
 """
 import sys
 
+import time
+
 import numpy as np
 import pytest
 
@@ -97,8 +99,14 @@ def run_parity(B, circ, chi, prec, shots, *, check_mps=True, tie=None, mode=0):
     lm, nt = sched(mode)
     say(f"parity n={circ.n} S={circ.n_shots} chi={chi} {prec} layer mode {lm} threads {nt}")
     eps = EPS[prec]
+    t0 = time.perf_counter()
     g = B.run_circuit(circ, chi, prec, eps, layer_mode=lm, layer_threads=nt)
-    ores = {s: ostn.run_shot(circ, s, chi_max=chi, eps_cut=eps) for s in shots}
+    say(f"  GPU run {time.perf_counter() - t0:.1f} s")
+    ores = {}
+    for s in shots:
+        t0 = time.perf_counter()
+        ores[s] = ostn.run_shot(circ, s, chi_max=chi, eps_cut=eps)
+        say(f"  oracle shot {s}: {time.perf_counter() - t0:.1f} s")
     tie = tie if tie is not None else (1e-9 if prec == "fp64" else 1e-4)
     cond = [s for s in shots if ores[s].cut_sensitivity <= MAX_SENS[prec]]
     skipped = len(shots) - len(cond)
