@@ -350,7 +350,7 @@ stn_status stn_set_layer_threads(stn_ctx *ctx, int threads);
 
 /* Largest doubled bond at which the fused layer kernel's left-to-right
  * sweep forms left-environment Grams instead of Householder QR (0: always
- * QR).  stn_init sets the largest its workspace allows (up to 256); values
+ * QR).  stn_init sets the largest its workspace allows (up to 512); values
  * above that are STN_EINVAL.  A tuning knob: results agree to rounding
  * order. */
 stn_status stn_set_layer_env(stn_ctx *ctx, int max_bond);

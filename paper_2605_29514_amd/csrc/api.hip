@@ -277,11 +277,12 @@ void plan_mps(Layout &L, int n, int S, int chi, size_t esz, int wmul, char *base
   // environment path of the fused kernel (forward state only): one Gram per
   // site of a span for doubled bonds up to eb
   // doubled bonds up to eb (the product scratch F = E B is eb x 2 eb); the
-  // packed Grams of a span share a store of n x ec^2 per shot, ec halved
+  // packed Grams of a span share a store of n x ec^2 per shot, ec lowered in steps of 32
   // (down to 32) until every shot's store fits the memory budget
-  const int64_t eb = wmul == 2 ? std::min<int64_t>(kEnvBond, 2 * chi_eff) : 0;
+  int64_t eb = wmul == 2 ? std::min<int64_t>(kEnvBond, 2 * chi_eff) : 0;
+  while (eb > 64 && (size_t)S * eb * 2 * eb * sizeof(c64) > kEnvFBudget) eb /= 2;
   int64_t ec = std::min<int64_t>(eb, kEnvStore);
-  while (ec > 32 && (size_t)S * n * ec * ec * sizeof(c64) > kEnvBudget) ec /= 2;
+  while (ec > 32 && (size_t)S * n * ec * ec * sizeof(c64) > kEnvBudget) ec -= 32;
   const int64_t Escap = (int64_t)n * ec * ec, Fscap = eb * 2 * eb;
   size_t o_Es = L.off((size_t)Escap * S * sizeof(c64)), o_Fs = L.off((size_t)Fscap * S * sizeof(c64));
   if (base) {

@@ -55,13 +55,18 @@ constexpr int kWorkWords = kPathBase + kPaths;
 enum { kPathEnv = 0, kPathQr, kPathEigLds, kPathEigGlobal, kPathEigGlobal129, kPathMaxOrder, kPathCholCycles,
        kPathJacGlobal, kPathCholQr, kPathEigNominal, kPathEigExec };
 // Largest doubled bond for which the fused kernel keeps the left-environment
-// Grams of a span (FP64 complex) instead of a QR sweep; the Grams of a span
-// are packed into a per-shot store of n x kEnvStore^2 elements (smaller when
-// the stores of all shots would pass kEnvBudget bytes), and a span whose
-// Grams do not fit takes the QR sweep.
-constexpr int kEnvBond = 256;
-constexpr int kEnvStore = 128;
-constexpr size_t kEnvBudget = (size_t)24 << 30;
+// Grams of a span (FP64 complex) instead of a QR sweep (halved while the
+// product scratch of all shots, kEnvBond x 2 kEnvBond each, would pass
+// kEnvFBudget bytes); the Grams of a span are packed into a per-shot store
+// of n x ec^2 elements, ec = kEnvStore lowered in steps of 32 until the
+// stores of all shots fit kEnvBudget bytes, and a span whose Grams do not
+// fit takes the QR sweep.  Sized for the 288 GB of one MI355X next to the
+// MPS and its workspace: with 1024 shots of 49 sites at chi_max 256 the
+// store takes 40 GB (ec = 224) and the product scratch 8.6 GB.
+constexpr int kEnvBond = 512;
+constexpr int kEnvStore = 256;
+constexpr size_t kEnvBudget = (size_t)40 << 30;
+constexpr size_t kEnvFBudget = (size_t)12 << 30;
 
 // Host-side recorder: when active, launches of the selected classes are
 // bracketed by HIP events on their stream.

@@ -124,10 +124,11 @@ __device__ inline Fallback fallback(const MpsDev &m, int s) {
 template <typename TA, typename TB_, typename TC, typename ACC, int NT>
 __device__ void blk_gemm(int M, int N, int K, const cplx<TA> *A, int lda, int opA,
                          const cplx<TB_> *B, int ldb, int opB, cplx<TC> *C, int ldc, char *lds, int lower = 0) {
-  // 512 threads: eight waves each take their own 16 x 32 output blocks
-  // straight from memory (the LDS-staged tile is shaped for up to four);
+  // 256 or more threads: each wave takes its own 16 x 32 output blocks
+  // straight from memory (measured faster than the LDS-staged tiles, which
+  // keep the whole block on one 32 x 32 tile at a time);
   // lower: output blocks wholly above the diagonal are skipped
-  if constexpr (NT >= 512) {
+  if constexpr (NT >= 256) {
     gemm_direct<TA, TB_, TC, ACC, NT>(M, N, K, A, lda, opA, B, ldb, opB, C, ldc, lower);
   } else {
     if (M <= kDirectGemm && N <= kDirectGemm && K <= kDirectGemm)
