@@ -45,7 +45,9 @@ def test_workspace_bytes(lib):
     assert b64 > b32 > 0
     assert b64 % 256 == 0
     big = lib.stn_workspace_bytes(ctypes.byref(cfg(n=49, S=1024, chi=256, prec=B.STN_FP32)))
-    assert 50e9 < big < 250e9                     # fits one 288 GB device
+    # the d=5 chi 256 bench context (238 GiB, its environment store included)
+    # leaves room on one 288 GB device next to the runtime's own allocations
+    assert 50e9 < big < 265e9
     for bad in (cfg(n=0), cfg(S=0), cfg(chi=0), cfg(prec=7), cfg(eps=-1.0), cfg(chi=4096)):
         assert lib.stn_workspace_bytes(ctypes.byref(bad)) == 0
 
