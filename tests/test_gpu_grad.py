@@ -96,6 +96,39 @@ def test_gradient_d3_memory(A, chi):
     check(A, circ, chi, "fp64")
 
 
+def test_gradient_matches_gpu_central_differences(A):
+    """The adjoint gradient against central differences (h = 1e-4) of the
+    GPU's own FP64 forward log P on a d=3 two-round memory experiment at chi
+    64 (exact: no truncation), one angle per rotation instance: the forward
+    runs the base angles and every +h / -h move of six round-2 angles as
+    shots of one batch with the same forced record (the first round's
+    gradient vanishes, every outcome there has probability 1/2 or 1)."""
+    import torch
+    P = 6
+    S = 1 + 2 * P
+    circ = W.memory_circuit(3, 2, S, seed=5, theta_nn=0.1, p=0.0, per_layer_params=True)
+    rec = np.array(ostn.run_shot(circ, 0, chi_max=64, eps_cut=EPS["fp64"]).record, np.uint8)
+    run = A.GradientRun(circ, 64, np.tile(rec, (S, 1)), "fp64", EPS["fp64"])
+    th0 = np.concatenate([op["theta"] for op in circ.ops if op["op"] == "rotate"], axis=1)[0]
+    picks = np.linspace(run.R // 2, run.R - 1, P).astype(int)
+    h = 1e-4
+    th = np.tile(th0, (S, 1))
+    for i, q in enumerate(picks):
+        th[1 + i, q] += h
+        th[1 + P + i, q] -= h
+    run.set_theta(torch.tensor(th, dtype=torch.float64, device="cuda:0"))
+    lp = run.forward().cpu().numpy()
+    g = run.backward().cpu().numpy()
+    assert not run.adjoint_truncated.any()
+    fd = (lp[1:1 + P] - lp[1 + P:]) / (2 * h)
+    ad = g[0, picks]
+    err = float(np.abs(fd - ad).max())
+    say(f"  adjoint {np.array2string(ad, precision=8)}\n  central {np.array2string(fd, precision=8)}\n"
+        f"  max abs diff {err:.2e}")
+    assert float(np.abs(ad).max()) > 1e-4
+    assert err <= 1e-6 * max(1.0, float(np.abs(ad).max()))
+
+
 def test_checkpoint_stretches_agree(A):
     """One stretch over the whole circuit and one per measurement give the
     same gradient (the adjoint state carries over between stretches)."""
